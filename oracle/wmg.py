@@ -1,0 +1,160 @@
+"""WMG preconditioners on the normal equations (oracle).
+
+System operator K = W^T W + lam I (eq. sys_ne, eq. sys_reg with the squared
+Tikhonov reading).  Let V_p denote the columns of H_L^T that belong to packet p
+(one coarsest-grid subproblem of Section 3.1.3; 4^L of them, each with
+(n/2^L)^2 unknowns).  The Galerkin coarse operator of a subproblem
+(eq. galerkin and the WTG box of Section 3.1.2) is A_p = V_p^T K V_p.
+
+Variants:
+  * additive_exact: M^-1 = sum_p V_p A_p^-1 V_p^T.  This is the additive form of
+    the wavelet two-grid scheme that Section 3.1.2 names, recursed to the
+    coarsest level, with exact coarsest solves (Cholesky, as in Section 4.1).
+  * additive_diag:  M^-1 = H_L^T diag(1/d) H_L with d_q = e_q^T H_L K H_L^T e_q
+    = ||W H_L^T e_q||^2 + lam, i.e. A_p replaced by its diagonal.  1/d := 0
+    where d = 0.  This is the reading used by the GPU path (the coarsest
+    problems are too large for dense factorisation at the benchmark sizes).
+  * WaveletCycle: the paper's multiplicative WTG (eq. wmg) and its hybrid
+    variant (LL correction, one residual update, then LH, HL, HH from that
+    residual; Section 3.1.2), recursed with exact coarsest solves.
+
+Parity status: packet_diagonal pinned by brute force against dense
+diag(H_L W^T W H_L^T) on small grids; the additive variants pinned by the
+block-diagonal exactness property (K = H_L^T B H_L with B block diagonal is
+inverted exactly).
+"""
+from __future__ import annotations
+
+import numpy as np
+import scipy.linalg as sla
+import scipy.sparse as sp
+
+from . import haar
+from .geometry import Geometry
+from .projector import angle_block
+
+
+def packet_diagonal(W_blocks, n: int, L: int, lam: float = 0.0) -> np.ndarray:
+    """d in quadrant layout [n][n]: squared column norms of W H_L^T, plus lam.
+
+    W_blocks: a CSR matrix W or an iterable of row blocks of W (e.g. per angle).
+    """
+    HT = haar.packet_matrix(n, L).T.tocsr()
+    if sp.issparse(W_blocks):
+        W_blocks = [W_blocks]
+    d = np.zeros(n * n)
+    for Wk in W_blocks:
+        Y = (Wk @ HT).tocsr()
+        d += np.asarray(Y.multiply(Y).sum(axis=0)).ravel()
+    return (d + lam).reshape(n, n)
+
+
+def packet_diagonal_by_angles(g: Geometry, L: int, lam: float = 0.0) -> np.ndarray:
+    """packet_diagonal streaming one angle block at a time (bounded memory)."""
+    return packet_diagonal((angle_block(g, k) for k in range(g.m)), g.n, L, lam)
+
+
+def apply_additive_diag(r: np.ndarray, d: np.ndarray, L: int) -> np.ndarray:
+    """z = H_L^T diag(1/d) H_L r (1/d := 0 where d == 0)."""
+    n = d.shape[0]
+    c = haar.packet_transform(np.asarray(r, dtype=np.float64).reshape(n, n), L)
+    inv = np.zeros_like(d)
+    nz = d != 0.0
+    inv[nz] = 1.0 / d[nz]
+    return haar.packet_adjoint(c * inv, L).ravel()
+
+
+def packet_columns(n: int, L: int) -> list[np.ndarray]:
+    """For each packet p, the quadrant-layout flat indices of its coefficients."""
+    cs = n >> L
+    idx = np.arange(n * n).reshape(n, n)
+    out = []
+    for pr in range(1 << L):
+        for pc in range(1 << L):
+            out.append(idx[pr * cs:(pr + 1) * cs, pc * cs:(pc + 1) * cs].ravel())
+    return out
+
+
+def galerkin_blocks(W: sp.csr_matrix, n: int, L: int, lam: float = 0.0):
+    """Cholesky factors of A_p = (W V_p)^T (W V_p) + lam I for every packet p.
+
+    W may be the sparse projection matrix or any dense factor F with K = F^T F.
+    """
+    HT = haar.packet_matrix(n, L).T.tocsc()
+    out = []
+    for cols in packet_columns(n, L):
+        WV = W @ HT[:, cols]
+        WV = WV.toarray() if sp.issparse(WV) else np.asarray(WV)
+        A = WV.T @ WV + lam * np.eye(len(cols))
+        out.append((cols, sla.cho_factor(A, lower=True)))
+    return out
+
+
+def apply_additive_exact(r: np.ndarray, blocks, n: int, L: int) -> np.ndarray:
+    """z = sum_p V_p A_p^-1 V_p^T r."""
+    c = haar.packet_transform(np.asarray(r, dtype=np.float64).reshape(n, n), L).ravel()
+    out = np.zeros_like(c)
+    for cols, fac in blocks:
+        out[cols] = sla.cho_solve(fac, c[cols])
+    return haar.packet_adjoint(out.reshape(n, n), L).ravel()
+
+
+class WaveletCycle:
+    """One wavelet multigrid cycle with exact coarsest solves (Section 3.1.2-3.1.3).
+
+    A cycle approximately solves K e = r with zero initial guess.  At a level
+    with operator A, the four Galerkin operators A_id = R_id A R_id^T use the
+    step operators R_id of eq. 1of4 - 4of4, and each coarse problem is treated
+    by the same cycle one level down (exact Cholesky solve at the coarsest level).
+
+    mode="multiplicative" (the WTG box, error propagation eq. wmg):
+        for id in LL, LH, HL, HH: e += R_id^T cycle(A_id, R_id (r - A e))
+    mode="hybrid" (the variant the experiments use, Section 3.1.2):
+        e = R_LL^T cycle(A_LL, R_LL r); r' = r - A e;
+        e += sum over LH, HL, HH of R_id^T cycle(A_id, R_id r')
+    mode="additive":
+        e = sum over all four of R_id^T cycle(A_id, R_id r)
+    Operators are formed densely, so this is for small grids only.
+    """
+
+    ORDER = ("LL", "LH", "HL", "HH")
+
+    def __init__(self, K: np.ndarray, n: int, L: int, mode: str = "hybrid"):
+        assert mode in ("multiplicative", "hybrid", "additive")
+        self.n, self.L, self.mode = n, L, mode
+        self.tree = self._build(np.asarray(K, dtype=np.float64), n, L)
+
+    def _build(self, A, s, levels):
+        if levels == 0:
+            return ("leaf", sla.cho_factor(A, lower=True))
+        ops = haar.step_operators_2d(s)
+        kids = {}
+        for name in self.ORDER:
+            R = ops[name].toarray()
+            kids[name] = (R, self._build(R @ A @ R.T, s // 2, levels - 1))
+        return ("node", A, kids)
+
+    def _cycle(self, node, r):
+        if node[0] == "leaf":
+            return sla.cho_solve(node[1], r)
+        _, A, kids = node
+        e = np.zeros_like(r)
+        if self.mode == "multiplicative":
+            for name in self.ORDER:
+                R, sub = kids[name]
+                e = e + R.T @ self._cycle(sub, R @ (r - A @ e))
+        elif self.mode == "hybrid":
+            R, sub = kids["LL"]
+            e = R.T @ self._cycle(sub, R @ r)
+            r2 = r - A @ e
+            for name in self.ORDER[1:]:
+                R, sub = kids[name]
+                e = e + R.T @ self._cycle(sub, R @ r2)
+        else:
+            for name in self.ORDER:
+                R, sub = kids[name]
+                e = e + R.T @ self._cycle(sub, R @ r)
+        return e
+
+    def __call__(self, r):
+        return self._cycle(self.tree, np.asarray(r, dtype=np.float64).ravel())
