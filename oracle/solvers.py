@@ -51,14 +51,19 @@ def _identity(v):
 
 
 def pcgls(W, b, tol=1e-3, max_iter=1000, lam=0.0, precond=None, fixed_iters=None,
-          callback=None) -> Result:
-    """Preconditioned CGLS.  fixed_iters runs exactly that many iterations."""
+          callback=None, store=None) -> Result:
+    """Preconditioned CGLS.  fixed_iters runs exactly that many iterations.
+
+    store, if given, is applied to every vector the recursion keeps (x, r, p,
+    q, s, z) right after it is formed; tests use it to model a lower storage
+    precision.  It is the identity otherwise."""
     Minv = precond or _identity
+    hook = store or _identity
     b = np.asarray(b, dtype=np.float64).ravel()
     x = np.zeros(W.shape[1])
-    r = b.copy()
-    s = W.T @ r - lam * x
-    z = Minv(s)
+    r = hook(b.copy())
+    s = hook(W.T @ r - lam * x)
+    z = hook(Minv(s))
     p = z.copy()
     gamma = float(s @ z)
     s0 = float(np.linalg.norm(s))
@@ -70,17 +75,17 @@ def pcgls(W, b, tol=1e-3, max_iter=1000, lam=0.0, precond=None, fixed_iters=None
     converged = False
     relres = 1.0
     while k < limit:
-        q = W @ p
+        q = hook(W @ p)
         delta = float(q @ q) + lam * float(p @ p)
         alpha = gamma / delta
-        x = x + alpha * p
-        r = r - alpha * q
-        s = W.T @ r - lam * x
-        z = Minv(s)
+        x = hook(x + alpha * p)
+        r = hook(r - alpha * q)
+        s = hook(W.T @ r - lam * x)
+        z = hook(Minv(s))
         gamma_new = float(s @ z)
         beta = gamma_new / gamma
         gamma = gamma_new
-        p = z + beta * p
+        p = hook(z + beta * p)
         k += 1
         relres = float(np.linalg.norm(s)) / s0
         hist.append(relres)
@@ -93,9 +98,14 @@ def pcgls(W, b, tol=1e-3, max_iter=1000, lam=0.0, precond=None, fixed_iters=None
 
 
 def gmres_right(W, b, tol=1e-3, restart=30, max_iter=1000, lam=0.0, precond=None,
-                fixed_iters=None) -> Result:
-    """Right-preconditioned restarted GMRES on (W^T W + lam I) M^-1 u = W^T b."""
+                fixed_iters=None, store=None) -> Result:
+    """Right-preconditioned restarted GMRES on (W^T W + lam I) M^-1 u = W^T b.
+
+    store, if given, is applied to every stored vector (basis vectors, the
+    new Krylov vector, x) right after it is formed; tests use it to model a
+    lower storage precision.  It is the identity otherwise."""
     Minv = precond or _identity
+    hook = store or _identity
 
     def K(v):
         return W.T @ (W @ v) + lam * v
@@ -122,17 +132,17 @@ def gmres_right(W, b, tol=1e-3, restart=30, max_iter=1000, lam=0.0, precond=None
         sn = np.zeros(restart)
         g = np.zeros(restart + 1)
         g[0] = beta
-        V[0] = r / beta
+        V[0] = hook(r / beta)
         j_done = 0
         for j in range(restart):
-            w = K(Minv(V[j]))
+            w = hook(K(Minv(V[j])))
             matvecs += 1
             for i in range(j + 1):           # modified Gram-Schmidt
                 H[i, j] = float(V[i] @ w)
                 w = w - H[i, j] * V[i]
             H[j + 1, j] = float(np.linalg.norm(w))
             if H[j + 1, j] != 0.0:
-                V[j + 1] = w / H[j + 1, j]
+                V[j + 1] = hook(w / H[j + 1, j])
             for i in range(j):               # previous rotations
                 t = cs[i] * H[i, j] + sn[i] * H[i + 1, j]
                 H[i + 1, j] = -sn[i] * H[i, j] + cs[i] * H[i + 1, j]
@@ -155,7 +165,7 @@ def gmres_right(W, b, tol=1e-3, restart=30, max_iter=1000, lam=0.0, precond=None
         y = np.zeros(j_done)
         for i in range(j_done - 1, -1, -1):      # back substitution
             y[i] = (g[i] - H[i, i + 1:j_done] @ y[i + 1:j_done]) / H[i, i]
-        x = x + Minv(V[:j_done].T @ y)
+        x = hook(x + Minv(V[:j_done].T @ y))
         if not converged and total < limit:
             r = f - K(x)                          # true residual at restart
             matvecs += 1

@@ -1,0 +1,90 @@
+// Device helpers shared by the kernels: wave64 reductions, fixed-order block
+// reductions and the last-block finalisation pattern (deterministic: partials
+// are summed in block order by whichever block finishes last).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "internal.h"
+
+namespace reco {
+
+template <typename T>
+__device__ __forceinline__ T clamp01(T v, T hi) {
+  return v < T(0) ? T(0) : (v > hi ? hi : v);
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+__device__ __forceinline__ int wave_min(int v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, 64));
+  return v;
+}
+__device__ __forceinline__ int wave_max(int v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+// Sum W values over a 256-thread block in a fixed order.  Result valid in
+// thread 0.  `sh` must hold 4*W doubles.
+template <int W>
+__device__ __forceinline__ void block_sum256(double (&v)[W], double* sh) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int i = 0; i < W; ++i) v[i] = wave_sum(v[i]);
+  if (lane == 0) {
+#pragma unroll
+    for (int i = 0; i < W; ++i) sh[wv * W + i] = v[i];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int i = 0; i < W; ++i) v[i] = ((sh[i] + sh[W + i]) + sh[2 * W + i]) + sh[3 * W + i];
+  }
+  __syncthreads();
+}
+
+// Each block contributes W partial sums; the last block to arrive sums them in
+// block order and calls fin(totals) from thread 0.  Returns nothing; the
+// counter is reset for the next use.  Block size must be 256.
+template <int W, typename F>
+__device__ __forceinline__ void reduce_and_finish(double (&v)[W], const RedScratch& red,
+                                                  int nblocks, int block_id, F fin) {
+  __shared__ double sh[4 * W];
+  __shared__ int am_last;
+  block_sum256<W>(v, sh);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int i = 0; i < W; ++i) red.partial[(size_t)block_id * W + i] = v[i];
+    __threadfence();
+    const unsigned t = atomicAdd(red.counter, 1u);
+    am_last = (t == (unsigned)nblocks - 1u);
+  }
+  __syncthreads();
+  if (!am_last) return;
+  __threadfence();
+  double acc[W];
+#pragma unroll
+  for (int i = 0; i < W; ++i) acc[i] = 0.0;
+  for (int b = threadIdx.x; b < nblocks; b += 256) {
+#pragma unroll
+    for (int i = 0; i < W; ++i)
+      acc[i] += __hip_atomic_load(&red.partial[(size_t)b * W + i], __ATOMIC_RELAXED,
+                                  __HIP_MEMORY_SCOPE_AGENT);
+  }
+  block_sum256<W>(acc, sh);
+  if (threadIdx.x == 0) {
+    fin(acc);
+    *red.counter = 0u;
+    __threadfence();
+  }
+}
+
+__device__ __forceinline__ bool finite(double v) { return __builtin_isfinite(v); }
+
+}  // namespace reco

@@ -1,0 +1,203 @@
+// Internal declarations of libreco: geometry object, per-angle tables, device
+// solver state, kernel launchers.  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+#include <cstdint>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/reco.h"
+
+namespace reco {
+
+// ---------------------------------------------------------------------------
+// Errors
+// ---------------------------------------------------------------------------
+void set_error(const std::string& msg);
+void clear_error();
+
+struct Error {
+  reco_status code;
+  std::string msg;
+};
+
+// Throwing helpers used inside the library; the ABI layer converts them.
+[[noreturn]] void fail(reco_status code, const std::string& msg);
+void check_hip(hipError_t e, const char* what, const char* file, int line);
+#define HIP_CHECK(expr) ::reco::check_hip((expr), #expr, __FILE__, __LINE__)
+
+// ---------------------------------------------------------------------------
+// Per-angle tables (host-computed in float64; float copies for the f32 path)
+// ---------------------------------------------------------------------------
+// Forward projector (ray driven).  For angle k let (a, b) = (cos, sin) when
+// |cos| >= |sin| ("major" = 0: the ray is walked row by row over the image),
+// else (sin, cos) ("major" = 1: walked column by column over the transposed
+// image).  At major index r the ray crosses the minor axis at pixel-index
+// position P(j, r) = A0 + j*inv + r*slope; the two pixels floor(P) and
+// floor(P)+1 are the only ones with nonzero weight, and with f = P - floor(P)
+//   w0/h = clamp((1/2 - f) * B + C, 0, Wmax),   w1/h = Wmax - w0/h
+// (the weights of one row add up to the row's chord h/|a|).
+struct FwdAngle {
+  double A0, inv, slope;
+  long long dP;        // slope in 32.32 fixed point
+  int major;
+  int pad_;
+  double B, C, Wmax;
+  float Bf, Cf, Wmaxf, padf_;
+};
+
+// Backprojector (pixel driven).  Pixel centre (X, Y) in pixel units from the
+// image centre projects to bin coordinate J = X c + Y s + (nb-1)/2; with
+// f = J - floor(J) the bins floor(J) and floor(J)+1 carry
+//   w0/h = clamp(C0 - f B, 0, Wmax),   w1/h = clamp(C1 + f B, 0, Wmax).
+struct BwdAngle {
+  double c, s, B, C0, C1, Wmax;
+  float cf, sf, Bf, C0f, C1f, Wmaxf;
+  double half_u_plus_v;  // (|c|+|s|)/2: half support of the trapezoid, bins
+  double inv_uv_d, cc_d; // 1/(uv) and (u+v)/(2uv) in direct form (setup kernels)
+  float inv_uv_f, cc_f, huv_f, padf_;
+};
+
+// ---------------------------------------------------------------------------
+// Geometry
+// ---------------------------------------------------------------------------
+struct Workspace;  // solver buffers (solve.hip)
+
+struct Geometry {
+  reco_geometry_desc desc{};
+  int n = 0, m = 0, nb = 0, L = 0, T = 1;  // L packet levels, T = 2^L
+  int ld = 0;                               // padded row length of image copies
+  double h = 0;
+  bool f64 = false;
+  int device = 0;
+
+  FwdAngle* d_fwd = nullptr;   // [m]
+  BwdAngle* d_bwd = nullptr;   // [m]
+  std::vector<FwdAngle> h_fwd;
+  std::vector<BwdAngle> h_bwd;
+
+  // packet diagonal (in-place tile layout, see wmg.hip), float64 always
+  double* d_diag64 = nullptr;   // [n*n]
+  void* d_diag = nullptr;       // [n*n] in the geometry dtype (for the apply)
+
+  // SIRT weights (lazily built): R [M], C [N] in the geometry dtype
+  std::mutex sirt_mu;
+  void* d_sirtR = nullptr;
+  void* d_sirtC = nullptr;
+
+  // pool of solver workspaces
+  std::mutex ws_mu;
+  std::vector<Workspace*> ws_free;
+
+  size_t N() const { return (size_t)n * n; }
+  size_t M() const { return (size_t)m * nb; }
+  size_t esize() const { return f64 ? 8 : 4; }
+  size_t padded_elems() const { return (size_t)n * ld; }
+  ~Geometry();
+};
+
+Geometry* create_geometry(const reco_geometry_desc& d, hipStream_t st);
+void build_angle_tables(Geometry& g);
+
+// ---------------------------------------------------------------------------
+// Device-side solver state (one per solve; arrays of them for batches)
+// ---------------------------------------------------------------------------
+struct SolverState {
+  double gamma;      // <s, z> of the current iterate
+  double beta;       // CG direction coefficient for the next p
+  double alpha;
+  double delta;
+  double pp;         // ||p||^2 of the current direction (Tikhonov term)
+  double s0;         // reference norm
+  double relres;
+  double lambda;
+  double tol;
+  int iter;          // completed iterations
+  int max_iter;
+  int fixed;         // run exactly max_iter iterations
+  int done;          // 0 running, 1 converged, 2 cap, 3 non-finite
+  int init;          // 1 after the initial step
+  int hist_cap;      // capacity of hist
+  double* hist;      // device array of relres per iteration (may be null)
+  // GMRES
+  int j;             // inner steps done in the current cycle
+  int restart;
+  double fnorm;      // ||W^T b||
+  double wnorm;      // norm of the last orthogonalised vector
+};
+
+// Reduction scratch handed to kernels that finish with a last-block step.
+struct RedScratch {
+  double* partial;          // [blocks * width]
+  unsigned int* counter;    // zero-initialised ticket counter
+  int capacity;             // blocks * width capacity
+};
+
+// ---------------------------------------------------------------------------
+// Kernel launchers (project.hip, backproject.hip, wmg.hip, vec.hip)
+// ---------------------------------------------------------------------------
+enum FwdMode { FWD_PLAIN = 0, FWD_CGLS = 1, FWD_SIRT = 2, FWD_COUNT = 3 };
+enum BwdMode { BWD_PLAIN = 0, BWD_CGLS = 1, BWD_SIRT = 2, BWD_AXPY = 3 };
+
+struct FwdArgs {
+  const void* imgP;    // [n][ld] padded image
+  const void* imgTP;   // [n][ld] padded transposed image
+  void* out;           // [m][nb]
+  const void* b;       // SIRT: measured data
+  const void* R;       // SIRT: inverse row sums
+  SolverState* st;     // CGLS/SIRT: state (may be null)
+  RedScratch red;      // CGLS: partials
+  unsigned long long* count;  // FWD_COUNT: nnz counter
+};
+
+struct BwdArgs {
+  const void* sino;    // [m][nb]
+  void* out;           // [n][n]
+  const void* x;       // extra-term source (CGLS: current x; AXPY: xin)
+  const void* f;       // AXPY: right-hand side term
+  const void* C;       // SIRT: inverse column sums
+  SolverState* st;
+  RedScratch red;
+  int x_ld = 0, x_off = 0;       // AXPY: layout of x
+  double sa = 1.0, sx = 0.0, sf = 0.0;  // AXPY: out = sa*W^T r + sx*x + sf*f
+};
+
+void launch_pad_transpose(const Geometry& g, const void* x, void* xP, void* xTP,
+                          hipStream_t st);
+void launch_forward(const Geometry& g, FwdMode mode, const FwdArgs& a, hipStream_t st);
+int forward_blocks(const Geometry& g);
+void launch_backward(const Geometry& g, BwdMode mode, const BwdArgs& a, hipStream_t st);
+int backward_blocks(const Geometry& g);
+
+// WMG apply (wmg.hip)
+enum WmgMode { WMG_PLAIN = 0, WMG_CGLS = 1, WMG_CGLS_INIT = 2, WMG_GMRES = 3 };
+struct WmgArgs {
+  const void* s;        // input image [n][n]
+  void* z;              // output plain [n][n] (may be null)
+  void* zP;             // output padded (may be null)
+  void* zTP;            // output padded transposed (may be null)
+  const void* pold;     // CGLS with lambda: previous direction
+  double lambda;
+  bool identity;        // no preconditioner: z = s
+  SolverState* st;
+  RedScratch red;
+};
+void launch_wmg(const Geometry& g, WmgMode mode, const WmgArgs& a, hipStream_t st);
+int wmg_blocks(const Geometry& g);
+void compute_packet_diagonal(Geometry& g, hipStream_t st);
+
+// vector kernels (vec.hip)
+void launch_fill(void* p, size_t count, bool f64, double value, hipStream_t st);
+void launch_copy(const void* src, void* dst, size_t count, bool f64, hipStream_t st);
+void launch_cgls_update(const Geometry& g, void* x, void* p, const void* zP, void* r,
+                        const void* q, SolverState* st, hipStream_t s);
+void launch_invert(void* v, size_t count, bool f64, hipStream_t st);
+void launch_state_init(SolverState* st, double tol, int max_iter, int fixed, double lambda,
+                       double* hist, int hist_cap, hipStream_t s);
+
+}  // namespace reco

@@ -1,0 +1,312 @@
+// Solver drivers: CGLS (Section 2.2.1 with an SPD preconditioner on the normal
+// equations), restarted right-preconditioned GMRES (eq. sys_prec) and SIRT
+// (eq. sirt_it).  The Krylov state stays on the device; scalars are float64.
+// The host only enqueues iterations and polls a pinned copy of the device
+// state every few iterations; once the device marks the solve finished every
+// further kernel of the chunk returns immediately.
+#include <chrono>
+#include <cmath>
+#include <cstring>
+
+#include "device_common.h"
+#include "solve.h"
+
+namespace reco {
+
+// ---------------------------------------------------------------------------
+// Workspaces
+// ---------------------------------------------------------------------------
+Workspace::~Workspace() {
+  auto f = [](void* p) { if (p) (void)hipFree(p); };
+  f(r); f(q); f(s); f(p); f(zP); f(zTP); f(xP); f(xTP); f(tmp); f(fvec);
+  f(partial); f(counter); f(st); f(hist); f(V); f(gm);
+  if (h_st) (void)hipHostFree(h_st);
+}
+
+static void alloc(void** p, size_t bytes) {
+  if (hipMalloc(p, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    fail(RECO_ENOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed");
+  }
+}
+
+Workspace* checkout_workspace(Geometry& g, hipStream_t st) {
+  {
+    std::lock_guard<std::mutex> lk(g.ws_mu);
+    if (!g.ws_free.empty()) {
+      Workspace* w = g.ws_free.back();
+      g.ws_free.pop_back();
+      return w;
+    }
+  }
+  std::unique_ptr<Workspace> w(new Workspace());
+  const size_t es = g.esize();
+  alloc(&w->r, es * g.M());
+  alloc(&w->q, es * g.M());
+  alloc(&w->s, es * g.N());
+  alloc(&w->p, es * g.N());
+  alloc(&w->zP, es * g.padded_elems());
+  alloc(&w->zTP, es * g.padded_elems());
+  alloc(&w->xP, es * g.padded_elems());
+  alloc(&w->xTP, es * g.padded_elems());
+  alloc(&w->tmp, es * std::max(g.N(), g.M()));
+  alloc(&w->fvec, es * g.N());
+  int cap = std::max(forward_blocks(g), std::max(backward_blocks(g), wmg_blocks(g)));
+  w->red_cap = cap * 4;
+  alloc((void**)&w->partial, sizeof(double) * w->red_cap);
+  alloc((void**)&w->counter, sizeof(unsigned) * 4);
+  alloc((void**)&w->st, sizeof(SolverState));
+  if (hipHostMalloc((void**)&w->h_st, sizeof(SolverState), hipHostMallocDefault) != hipSuccess)
+    fail(RECO_ENOMEM, "pinned host allocation failed");
+  HIP_CHECK(hipMemsetAsync(w->counter, 0, sizeof(unsigned) * 4, st));
+  // zero padding columns of the padded image copies once; kernels only write interiors
+  launch_fill(w->zP, g.padded_elems(), g.f64, 0.0, st);
+  launch_fill(w->zTP, g.padded_elems(), g.f64, 0.0, st);
+  return w.release();
+}
+
+void return_workspace(Geometry& g, Workspace* w) {
+  std::lock_guard<std::mutex> lk(g.ws_mu);
+  g.ws_free.push_back(w);
+}
+
+void release_workspaces(Geometry& g) {
+  std::lock_guard<std::mutex> lk(g.ws_mu);
+  for (Workspace* w : g.ws_free) delete w;
+  g.ws_free.clear();
+}
+
+void ensure_history(Workspace& w, int cap) {
+  if (cap <= w.hist_cap) return;
+  if (w.hist) (void)hipFree(w.hist);
+  w.hist = nullptr;
+  w.hist_cap = 0;
+  alloc((void**)&w.hist, sizeof(double) * cap);
+  w.hist_cap = cap;
+}
+
+RedScratch red_of(Workspace& w, int slot) {
+  RedScratch r;
+  r.partial = w.partial;
+  r.counter = w.counter + slot;
+  r.capacity = w.red_cap;
+  return r;
+}
+
+struct Lease {
+  Geometry& g;
+  Workspace* w;
+  Lease(Geometry& gg, hipStream_t st) : g(gg), w(checkout_workspace(gg, st)) {}
+  ~Lease() { return_workspace(g, w); }
+};
+
+static void validate_opts(const reco_solve_opts& o, bool gmres) {
+  if (!(o.tol > 0.0) && o.fixed_iters <= 0) fail(RECO_EINVAL, "tol must be > 0");
+  if (o.max_iter < 1 && o.fixed_iters <= 0) fail(RECO_EINVAL, "max_iter must be >= 1");
+  if (!(o.lambda >= 0.0)) fail(RECO_EINVAL, "lambda must be >= 0");
+  if (o.precond != RECO_PRECOND_NONE && o.precond != RECO_PRECOND_WMG)
+    fail(RECO_EINVAL, "unknown preconditioner");
+  if (gmres && (o.restart < 1 || o.restart > 64)) fail(RECO_EINVAL, "restart must be in [1, 64]");
+  if (o.history_cap < 0) fail(RECO_EINVAL, "history_cap must be >= 0");
+  if (o.check_every < 0) fail(RECO_EINVAL, "check_every must be >= 0");
+}
+
+static reco_status status_of(int done) {
+  switch (done) {
+    case 1: return RECO_OK;
+    case 2: return RECO_ENOTCONV;
+    case 3: return RECO_ENUMERIC;
+    default: return RECO_ENOTCONV;
+  }
+}
+
+static void poll_state(Workspace& w, hipStream_t st) {
+  HIP_CHECK(hipMemcpyAsync(w.h_st, w.st, sizeof(SolverState), hipMemcpyDeviceToHost, st));
+  HIP_CHECK(hipStreamSynchronize(st));
+}
+
+static void finish_info(Workspace& w, const reco_solve_opts& o, reco_solve_info* info,
+                        int matvecs, double ms, hipStream_t st) {
+  const SolverState& s = *w.h_st;
+  if (o.history && o.history_cap > 0 && s.iter > 0 && w.hist) {
+    const int cnt = std::min(std::min(o.history_cap, s.iter), w.hist_cap);
+    HIP_CHECK(hipMemcpyAsync(o.history, w.hist, sizeof(double) * cnt, hipMemcpyDeviceToHost, st));
+    HIP_CHECK(hipStreamSynchronize(st));
+  }
+  if (info) {
+    info->iters = s.iter;
+    info->matvecs = matvecs;
+    info->relres = s.relres;
+    info->status = status_of(s.done);
+    info->reserved = 0;
+    info->elapsed_ms = ms;
+  }
+}
+
+static double now_ms() {
+  return std::chrono::duration<double, std::milli>(
+             std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+// Run `step` repeatedly until the device reports done, polling every few calls.
+template <typename F>
+static void drive(Workspace& w, const reco_solve_opts& o, int limit, hipStream_t st, F step) {
+  int launched = 0;
+  int chunk = o.check_every > 0 ? o.check_every : 2;
+  for (;;) {
+    const int todo = std::min(chunk, limit - launched);
+    for (int i = 0; i < todo; ++i) step();
+    launched += todo;
+    poll_state(w, st);
+    if (w.h_st->done || launched >= limit) break;
+    if (o.check_every == 0) chunk = std::min(chunk * 2, 16);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// CGLS
+// ---------------------------------------------------------------------------
+// One iteration (4 launches):
+//   K1: q = W z + beta q   (= W p_new),  delta = ||q||^2 + lambda ||p_new||^2,  alpha
+//   K7: p = z + beta p;  x += alpha p;  r -= alpha q
+//   K2: s = W^T r - lambda x
+//   K4: z = M^-1 s;  gamma' = <s,z>, beta = gamma'/gamma, relres = ||s||/||s_0||
+void cgls_iteration(Geometry& g, Workspace& w, void* x, const reco_solve_opts& o, hipStream_t st) {
+  FwdArgs fa{};
+  fa.imgP = w.zP;
+  fa.imgTP = w.zTP;
+  fa.out = w.q;
+  fa.st = w.st;
+  fa.red = red_of(w, 0);
+  launch_forward(g, FWD_CGLS, fa, st);
+  launch_cgls_update(g, x, w.p, w.zP, w.r, w.q, w.st, st);
+  BwdArgs ba{};
+  ba.sino = w.r;
+  ba.out = w.s;
+  ba.x = x;
+  ba.st = w.st;
+  launch_backward(g, BWD_CGLS, ba, st);
+  WmgArgs wa{};
+  wa.s = w.s;
+  wa.zP = w.zP;
+  wa.zTP = w.zTP;
+  wa.pold = w.p;
+  wa.lambda = o.lambda;
+  wa.identity = o.precond == RECO_PRECOND_NONE;
+  wa.st = w.st;
+  wa.red = red_of(w, 1);
+  launch_wmg(g, WMG_CGLS, wa, st);
+}
+
+void cgls_setup(Geometry& g, Workspace& w, const void* b, void* x, const reco_solve_opts& o,
+                hipStream_t st) {
+  const bool fixed = o.fixed_iters > 0;
+  const int limit = fixed ? o.fixed_iters : o.max_iter;
+  ensure_history(w, limit);
+  launch_state_init(w.st, o.tol, limit, fixed ? 1 : 0, o.lambda, w.hist, limit, st);
+  launch_fill(x, g.N(), g.f64, 0.0, st);
+  launch_fill(w.p, g.N(), g.f64, 0.0, st);
+  launch_fill(w.q, g.M(), g.f64, 0.0, st);
+  launch_copy(b, w.r, g.M(), g.f64, st);
+  BwdArgs ba{};
+  ba.sino = w.r;
+  ba.out = w.s;
+  ba.x = x;
+  ba.st = w.st;
+  launch_backward(g, BWD_CGLS, ba, st);
+  WmgArgs wa{};
+  wa.s = w.s;
+  wa.zP = w.zP;
+  wa.zTP = w.zTP;
+  wa.pold = w.p;
+  wa.lambda = o.lambda;
+  wa.identity = o.precond == RECO_PRECOND_NONE;
+  wa.st = w.st;
+  wa.red = red_of(w, 1);
+  launch_wmg(g, WMG_CGLS_INIT, wa, st);
+}
+
+reco_status solve_cgls(Geometry& g, const void* b, void* x, const reco_solve_opts& o,
+                       reco_solve_info* info, hipStream_t st) {
+  validate_opts(o, false);
+  const double t0 = now_ms();
+  Lease lease(g, st);
+  Workspace& w = *lease.w;
+  cgls_setup(g, w, b, x, o, st);
+  const int limit = o.fixed_iters > 0 ? o.fixed_iters : o.max_iter;
+  drive(w, o, limit, st, [&] { cgls_iteration(g, w, x, o, st); });
+  const SolverState& s = *w.h_st;
+  finish_info(w, o, info, 1 + s.iter, now_ms() - t0, st);
+  return status_of(s.done);
+}
+
+// ---------------------------------------------------------------------------
+// SIRT
+// ---------------------------------------------------------------------------
+void ensure_sirt_weights(Geometry& g, hipStream_t st) {
+  std::lock_guard<std::mutex> lk(g.sirt_mu);
+  if (g.d_sirtR) return;
+  const size_t es = g.esize();
+  void *R = nullptr, *C = nullptr, *ones = nullptr, *P = nullptr, *PT = nullptr;
+  alloc(&R, es * g.M());
+  alloc(&C, es * g.N());
+  alloc(&ones, es * std::max(g.N(), g.M()));
+  alloc(&P, es * g.padded_elems());
+  alloc(&PT, es * g.padded_elems());
+  launch_fill(ones, std::max(g.N(), g.M()), g.f64, 1.0, st);
+  launch_pad_transpose(g, ones, P, PT, st);
+  FwdArgs fa{};
+  fa.imgP = P;
+  fa.imgTP = PT;
+  fa.out = R;
+  launch_forward(g, FWD_PLAIN, fa, st);
+  launch_invert(R, g.M(), g.f64, st);
+  BwdArgs ba{};
+  ba.sino = ones;
+  ba.out = C;
+  launch_backward(g, BWD_PLAIN, ba, st);
+  launch_invert(C, g.N(), g.f64, st);
+  HIP_CHECK(hipStreamSynchronize(st));
+  (void)hipFree(ones);
+  (void)hipFree(P);
+  (void)hipFree(PT);
+  g.d_sirtR = R;
+  g.d_sirtC = C;
+}
+
+reco_status solve_sirt(Geometry& g, const void* b, void* x, const reco_solve_opts& o,
+                       reco_solve_info* info, hipStream_t st) {
+  validate_opts(o, false);
+  const double t0 = now_ms();
+  ensure_sirt_weights(g, st);
+  Lease lease(g, st);
+  Workspace& w = *lease.w;
+  const bool fixed = o.fixed_iters > 0;
+  const int limit = fixed ? o.fixed_iters : o.max_iter;
+  ensure_history(w, limit);
+  launch_state_init(w.st, o.tol, limit, fixed ? 1 : 0, 0.0, w.hist, limit, st);
+  launch_fill(x, g.N(), g.f64, 0.0, st);
+  drive(w, o, limit, st, [&] {
+    launch_pad_transpose(g, x, w.xP, w.xTP, st);
+    FwdArgs fa{};
+    fa.imgP = w.xP;
+    fa.imgTP = w.xTP;
+    fa.out = w.r;
+    fa.b = b;
+    fa.R = g.d_sirtR;
+    fa.st = w.st;
+    launch_forward(g, FWD_SIRT, fa, st);
+    BwdArgs ba{};
+    ba.sino = w.r;
+    ba.out = x;
+    ba.C = g.d_sirtC;
+    ba.st = w.st;
+    ba.red = red_of(w, 2);
+    launch_backward(g, BWD_SIRT, ba, st);
+  });
+  const SolverState& s = *w.h_st;
+  finish_info(w, o, info, s.iter, now_ms() - t0, st);
+  return status_of(s.done);
+}
+
+}  // namespace reco

@@ -1,0 +1,353 @@
+// Wavelet multigrid preconditioner, additive form with packet-diagonal
+// coarsest solves:  z = H_L^T diag(1/(d + lambda)) H_L s.
+//
+// H_L is the full Haar packet transform of L = ell - 1 levels (eq. intops,
+// eq. intops_wav, eq. 1of4 - 4of4, recursed into every subband as in Section
+// 3.1.3).  Each of its basis functions is a +-2^-L Walsh pattern on one
+// T x T pixel tile (T = 2^L), so the transform is a tile-local 2D
+// Walsh-Hadamard transform.  Coefficients are kept "in place": the
+// coefficient stored at pixel (iy, ix) belongs to tile (iy >> L, ix >> L) and
+// its level-l code in x (y) is bit l-1 of ix (iy) within the tile (0 = scaling
+// function, 1 = wavelet).
+//
+// d_q = ||W H_L^T e_q||^2 is the diagonal of the Galerkin operators of the
+// coarsest subproblems in the packet basis (eq. galerkin).  It is computed once
+// per geometry, tile by tile: for every angle and every detector bin crossing a
+// tile, the tile's weights are Walsh-transformed across the lanes of a wave and
+// their squares are accumulated in float64 by the wave that owns the tile, in
+// a fixed order (deterministic, no atomics).
+#include "device_common.h"
+#include "timing.h"
+
+namespace reco {
+
+namespace {
+
+// ------------------------------- apply ------------------------------------
+template <typename T>
+struct WmgK {
+  const T* s;
+  T* z;
+  T* zP;
+  T* zTP;
+  const T* pold;
+  const T* d;
+  SolverState* st;
+  RedScratch red;
+  int n, ld;
+  double lambda;
+};
+
+template <typename T, int L>
+__device__ __forceinline__ void wht_region(T (&tile)[32][33]) {
+  // butterflies along x (columns within rows) then along y
+#pragma unroll
+  for (int b = 0; b < L; ++b) {
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int pidx = threadIdx.x + 256 * q;   // 512 pairs: 32 rows x 16 pairs
+      const int row = pidx >> 4, pi = pidx & 15;
+      const int xa = ((pi >> b) << (b + 1)) | (pi & ((1 << b) - 1));
+      const int xb = xa | (1 << b);
+      const T u = tile[row][xa], v = tile[row][xb];
+      tile[row][xa] = u + v;
+      tile[row][xb] = u - v;
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int b = 0; b < L; ++b) {
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int pidx = threadIdx.x + 256 * q;
+      const int col = pidx & 31, pi = pidx >> 5;
+      const int ya = ((pi >> b) << (b + 1)) | (pi & ((1 << b) - 1));
+      const int yb = ya | (1 << b);
+      const T u = tile[ya][col], v = tile[yb][col];
+      tile[ya][col] = u + v;
+      tile[yb][col] = u - v;
+    }
+    __syncthreads();
+  }
+}
+
+template <typename T, int L, int MODE, bool IDENT>
+__global__ __launch_bounds__(256) void k_wmg(WmgK<T> a) {
+  if (a.st && a.st->done) return;   // solver finished: later launches are no-ops
+  __shared__ T tile[32][33];
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  const int x0 = blockIdx.x * 32, y0 = blockIdx.y * 32;
+  const int n = a.n;
+  T sv[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int r = ty + 8 * i, iy = y0 + r, ix = x0 + tx;
+    sv[i] = (iy < n && ix < n) ? a.s[(size_t)iy * n + ix] : T(0);
+    tile[r][tx] = sv[i];
+  }
+  __syncthreads();
+  if constexpr (!IDENT) {
+    wht_region<T, L>(tile);
+    const double scale = 1.0 / (double)(1u << (2 * L));   // 4^-L, exact
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int r = ty + 8 * i, iy = y0 + r, ix = x0 + tx;
+      double inv = 0.0;
+      if (iy < n && ix < n) {
+        const double dd = (double)a.d[(size_t)iy * n + ix] + a.lambda;
+        inv = dd != 0.0 ? scale / dd : 0.0;
+      }
+      tile[r][tx] = (T)((double)tile[r][tx] * inv);
+    }
+    __syncthreads();
+    wht_region<T, L>(tile);
+  }
+  T zv[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int r = ty + 8 * i, iy = y0 + r, ix = x0 + tx;
+    zv[i] = tile[r][tx];
+    if (iy < n && ix < n) {
+      if (a.z) a.z[(size_t)iy * n + ix] = zv[i];
+      if (a.zP) a.zP[(size_t)iy * a.ld + ix + 2] = zv[i];
+    }
+  }
+  if (a.zTP) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int r = ty + 8 * i;
+      const int ox = x0 + r, oy = y0 + tx;
+      if (ox < n && oy < n) a.zTP[(size_t)ox * a.ld + oy + 2] = tile[tx][r];
+    }
+  }
+  if constexpr (MODE == WMG_CGLS || MODE == WMG_CGLS_INIT) {
+    double v[4] = {0.0, 0.0, 0.0, 0.0};   // <s,z>, ||s||^2, ||z||^2, <z,p_old>
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int r = ty + 8 * i, iy = y0 + r, ix = x0 + tx;
+      const double s = (double)sv[i], z = (double)zv[i];
+      v[0] += s * z;
+      v[1] += s * s;
+      v[2] += z * z;
+      if (MODE == WMG_CGLS && a.lambda != 0.0 && iy < n && ix < n)
+        v[3] += z * (double)a.pold[(size_t)iy * n + ix];
+    }
+    SolverState* st = a.st;
+    reduce_and_finish<4>(v, a.red, gridDim.x * gridDim.y, blockIdx.y * gridDim.x + blockIdx.x,
+                         [st](double (&t)[4]) {
+                           if (MODE == WMG_CGLS_INIT) {
+                             st->gamma = t[0];
+                             st->s0 = sqrt(t[1]);
+                             st->beta = 0.0;
+                             st->pp = t[2];
+                             st->relres = 1.0;
+                             st->iter = 0;
+                             st->init = 1;
+                             if (!finite(st->s0) || !finite(t[0])) st->done = 3;
+                             else if (st->s0 == 0.0) { st->done = 1; st->relres = 0.0; }
+                           } else {
+                             const double g = t[0];
+                             const double beta = g / st->gamma;
+                             st->pp = t[2] + 2.0 * beta * t[3] + beta * beta * st->pp;
+                             st->beta = beta;
+                             st->gamma = g;
+                             st->iter += 1;
+                             const double rr = sqrt(t[1]) / st->s0;
+                             st->relres = rr;
+                             if (st->hist && st->iter <= st->hist_cap) st->hist[st->iter - 1] = rr;
+                             if (!finite(rr) || !finite(beta)) st->done = 3;
+                             else if (st->fixed) { if (st->iter >= st->max_iter) st->done = 1; }
+                             else if (rr <= st->tol) st->done = 1;
+                             else if (st->iter >= st->max_iter) st->done = 2;
+                             else if (g == 0.0) st->done = 1;
+                           }
+                         });
+  }
+}
+
+template <typename T, int L>
+void wmg_launch_L(const Geometry& g, WmgMode mode, const WmgArgs& a, hipStream_t st) {
+  WmgK<T> k;
+  k.s = (const T*)a.s;
+  k.z = (T*)a.z;
+  k.zP = (T*)a.zP;
+  k.zTP = (T*)a.zTP;
+  k.pold = (const T*)a.pold;
+  k.d = (const T*)g.d_diag;
+  k.st = a.st;
+  k.red = a.red;
+  k.n = g.n;
+  k.ld = g.ld;
+  k.lambda = a.lambda;
+  dim3 grid((g.n + 31) / 32, (g.n + 31) / 32);
+  TimedLaunch tl(TK_WMG, st);
+#define RECO_WMG_CASE(M)                                                                   \
+  case M:                                                                                  \
+    if (a.identity) hipLaunchKernelGGL((k_wmg<T, L, M, true>), grid, dim3(256), 0, st, k); \
+    else hipLaunchKernelGGL((k_wmg<T, L, M, false>), grid, dim3(256), 0, st, k);           \
+    break;
+  switch (mode) {
+    RECO_WMG_CASE(WMG_PLAIN)
+    RECO_WMG_CASE(WMG_CGLS)
+    RECO_WMG_CASE(WMG_CGLS_INIT)
+    RECO_WMG_CASE(WMG_GMRES)
+  }
+#undef RECO_WMG_CASE
+  HIP_CHECK(hipGetLastError());
+}
+
+template <typename T>
+void wmg_launch(const Geometry& g, WmgMode mode, const WmgArgs& a, hipStream_t st) {
+  switch (a.identity ? 0 : g.L) {
+    case 0: wmg_launch_L<T, 0>(g, mode, a, st); break;
+    case 1: wmg_launch_L<T, 1>(g, mode, a, st); break;
+    case 2: wmg_launch_L<T, 2>(g, mode, a, st); break;
+    case 3: wmg_launch_L<T, 3>(g, mode, a, st); break;
+    case 4: wmg_launch_L<T, 4>(g, mode, a, st); break;
+    case 5: wmg_launch_L<T, 5>(g, mode, a, st); break;
+    default: fail(RECO_EINVAL, "unsupported number of packet levels");
+  }
+}
+
+// --------------------------- packet diagonal --------------------------------
+// Lane layout: a tile of S = T*T pixels is spread over the 64 lanes of a wave
+// (E = S/64 pixels per lane when S >= 64, element e = r*64 + lane) or several
+// tiles share a wave (G = 64/S tiles, element e = lane % S).  Element e is the
+// tile pixel (ly, lx) = (e >> L, e & (T-1)).
+template <typename T, int L>
+__global__ __launch_bounds__(256) void k_packet_diag(const BwdAngle* __restrict__ ang, double* d64,
+                                                     T* dT, int n, int m, int nb, double h) {
+  constexpr int Tt = 1 << L;
+  constexpr int S = Tt * Tt;
+  constexpr int E = S >= 64 ? S / 64 : 1;
+  constexpr int G = S >= 64 ? 1 : 64 / S;
+  constexpr int LB = S >= 64 ? 6 : 2 * L;   // element bits held across lanes
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int tiles_x = n / Tt;
+  const int ntiles = tiles_x * tiles_x;
+  const int tile = (blockIdx.x * 4 + wv) * G + (S >= 64 ? 0 : lane / S);
+  const bool active = tile < ntiles;
+  const int tyT = active ? tile / tiles_x : 0, txT = active ? tile % tiles_x : 0;
+  const double hc = 0.5 * (n - 1), hb = 0.5 * (nb - 1);
+  const double Xt = txT * Tt + 0.5 * (Tt - 1) - hc;   // tile centre, pixel units
+  const double Yt = tyT * Tt + 0.5 * (Tt - 1) - hc;
+  T dXp[E], dYp[E];
+#pragma unroll
+  for (int r = 0; r < E; ++r) {
+    const int e = (S >= 64) ? (r * 64 + lane) : (lane % S);
+    dXp[r] = T((e & (Tt - 1)) - 0.5 * (Tt - 1));
+    dYp[r] = T((e >> L) - 0.5 * (Tt - 1));
+  }
+  double acc[E];
+#pragma unroll
+  for (int r = 0; r < E; ++r) acc[r] = 0.0;
+
+  for (int k = 0; k < m; ++k) {
+    const BwdAngle A = ang[k];
+    const double Jt = fma(Xt, A.c, fma(Yt, A.s, hb));
+    const double jbase = floor(Jt);
+    const T rel = (T)(Jt - jbase);
+    T c, s, Bq, Cq, Wm;
+    if constexpr (sizeof(T) == 4) { c = A.cf; s = A.sf; Bq = A.inv_uv_f; Cq = A.cc_f; Wm = A.Wmaxf; }
+    else { c = A.c; s = A.s; Bq = A.inv_uv_d; Cq = A.cc_d; Wm = A.Wmax; }
+    T Jp[E];
+#pragma unroll
+    for (int r = 0; r < E; ++r) Jp[r] = fma(dXp[r], c, fma(dYp[r], s, rel));
+    // bins with nonzero weight satisfy |jj - rel| < Tt * (u+v)/2 (+1 for rel in [0,1))
+    const double reach = Tt * A.half_u_plus_v;
+    const int jlo = (int)floor(-reach), jhi = (int)ceil(1.0 + reach);
+    const int jb = (int)jbase;
+    for (int jj = jlo; jj <= jhi; ++jj) {
+      const int j = jb + jj;
+      const bool inb = active && j >= 0 && j < nb;
+      T w[E];
+#pragma unroll
+      for (int r = 0; r < E; ++r) {
+        const T dist = fabs(T(jj) - Jp[r]);
+        w[r] = inb ? clamp01<T>(fma(-dist, Bq, Cq), Wm) : T(0);
+      }
+      // Walsh-Hadamard transform over the tile's S elements
+#pragma unroll
+      for (int b = 0; b < 2 * L; ++b) {
+        if (b < LB) {
+#pragma unroll
+          for (int r = 0; r < E; ++r) {
+            const T o = __shfl_xor(w[r], 1 << b, 64);
+            w[r] = (lane >> b) & 1 ? o - w[r] : w[r] + o;
+          }
+        } else {
+          const int rb = 1 << (b - LB);
+#pragma unroll
+          for (int r = 0; r < E; ++r) {
+            if (!(r & rb)) {
+              const T u = w[r], v = w[r | rb];
+              w[r] = u + v;
+              w[r | rb] = u - v;
+            }
+          }
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < E; ++r) {
+        const double q = (double)w[r];
+        acc[r] = fma(q, q, acc[r]);
+      }
+    }
+  }
+  if (active) {
+    const double scale = h * h / (double)(1u << (2 * L));
+#pragma unroll
+    for (int r = 0; r < E; ++r) {
+      const int e = (S >= 64) ? (r * 64 + lane) : (lane % S);
+      const int iy = tyT * Tt + (e >> L), ix = txT * Tt + (e & (Tt - 1));
+      const double v = acc[r] * scale;
+      d64[(size_t)iy * n + ix] = v;
+      dT[(size_t)iy * n + ix] = (T)v;
+    }
+  }
+}
+
+template <typename T, int L>
+void diag_launch_L(Geometry& g, hipStream_t st) {
+  constexpr int S = (1 << L) * (1 << L);
+  constexpr int G = S >= 64 ? 1 : 64 / S;
+  const int ntiles = (g.n >> L) * (g.n >> L);
+  const int tiles_per_block = 4 * G;
+  const int blocks = (ntiles + tiles_per_block - 1) / tiles_per_block;
+  TimedLaunch tl(TK_PACKET_DIAG, st);
+  hipLaunchKernelGGL((k_packet_diag<T, L>), dim3(blocks), dim3(256), 0, st, g.d_bwd, g.d_diag64,
+                     (T*)g.d_diag, g.n, g.m, g.nb, g.h);
+  HIP_CHECK(hipGetLastError());
+}
+
+template <typename T>
+void diag_launch(Geometry& g, hipStream_t st) {
+  switch (g.L) {
+    case 0: diag_launch_L<T, 0>(g, st); break;
+    case 1: diag_launch_L<T, 1>(g, st); break;
+    case 2: diag_launch_L<T, 2>(g, st); break;
+    case 3: diag_launch_L<T, 3>(g, st); break;
+    case 4: diag_launch_L<T, 4>(g, st); break;
+    case 5: diag_launch_L<T, 5>(g, st); break;
+    default: fail(RECO_EINVAL, "unsupported number of packet levels");
+  }
+}
+
+}  // namespace
+
+int wmg_blocks(const Geometry& g) {
+  const int t = (g.n + 31) / 32;
+  return t * t;
+}
+
+void launch_wmg(const Geometry& g, WmgMode mode, const WmgArgs& a, hipStream_t st) {
+  if (g.f64) wmg_launch<double>(g, mode, a, st);
+  else wmg_launch<float>(g, mode, a, st);
+}
+
+void compute_packet_diagonal(Geometry& g, hipStream_t st) {
+  if (g.f64) diag_launch<double>(g, st);
+  else diag_launch<float>(g, st);
+}
+
+}  // namespace reco

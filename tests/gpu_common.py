@@ -1,0 +1,58 @@
+"""Helpers for GPU parity tests: oracle systems cached per geometry, tensor moves."""
+import functools
+import math
+
+import numpy as np
+
+import inputs
+from oracle import wmg
+from oracle.geometry import Geometry as OG
+from oracle.projector import system_matrix
+
+
+@functools.lru_cache(maxsize=6)
+def oracle_W(n, m, nb):
+    return system_matrix(OG(n, m, nb))
+
+
+@functools.lru_cache(maxsize=6)
+def oracle_d(n, m, nb, L):
+    return wmg.packet_diagonal(oracle_W(n, m, nb), n, L)
+
+
+def rel(a, b):
+    a = np.asarray(a, dtype=np.float64).ravel()
+    b = np.asarray(b, dtype=np.float64).ravel()
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+def to_gpu(a, dtype):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a).astype(
+        np.float64 if dtype == torch.float64 else np.float32)).cuda()
+
+
+def to_np(t):
+    import torch
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+def phantom_and_data(n, m, nb, n_ellipses, seed, noise=0.0, dtype64=False):
+    """Seeded phantom, oracle sinogram b = W x (+ Gaussian noise), rounded to the storage type."""
+    x = inputs.ellipse_phantom(n, n_ellipses, seed)
+    W = oracle_W(n, m, nb)
+    b = W @ x.ravel()
+    if noise:
+        b = b + noise * np.abs(b).max() * inputs.standard_normal(b.size, seed + 500000)
+    if not dtype64:
+        b = b.astype(np.float32).astype(np.float64)
+    return x, b
+
+
+def print_case(*args):
+    print("CASE", *args, flush=True)
+
+
+SQRT2 = math.sqrt(2.0)

@@ -1,0 +1,120 @@
+"""GPU parity of the operators against the CPU float64 oracle (through the C ABI).
+
+Tolerances: float32 path relative L2 <= 1e-5 (projector, backprojector, WMG
+apply), float64 path <= 1e-12; packet diagonal elementwise relative 1e-5 / 1e-12.
+"""
+import numpy as np
+import pytest
+
+from gpu_common import oracle_W, oracle_d, print_case, rel, to_gpu, to_np
+from oracle import wmg
+from oracle.geometry import Geometry as OG
+from oracle.projector import pixel_column, ray_rows
+
+torch = pytest.importorskip("torch")
+reco = pytest.importorskip("paper_1310_0956_amd")
+
+pytestmark = pytest.mark.gpu
+
+# (n, m, nb, levels, f64): ragged sizes, the paper's 40x40 geometry, the 64^2 FP64
+# workload, axis-only and 45-degree angle sets, a single pixel-pair image.
+CASES = [
+    (24, 18, 35, 3, False),
+    (40, 100, 40, 2, False),
+    (64, 90, 64, 2, True),
+    (64, 90, 64, 2, False),
+    (48, 2, 70, 2, False),
+    (32, 4, 45, 4, True),
+    (2, 3, 3, 1, False),
+    (16, 1, 1, 2, True),
+    (128, 37, 182, 3, False),
+]
+TOL = {False: 1e-5, True: 1e-12}
+
+
+def _img(n, seed):
+    rng = np.random.default_rng(seed)
+    return rng.random((n, n)) + (rng.random((n, n)) > 0.8)
+
+
+@pytest.mark.parametrize("n,m,nb,lv,f64", CASES)
+def test_project_backproject_wmg_parity(n, m, nb, lv, f64):
+    print_case("operators", n, m, nb, lv, f64)
+    dt = torch.float64 if f64 else torch.float32
+    g = reco.Geometry(n, m, nb, lv, reco.F64 if f64 else reco.F32)
+    W = oracle_W(n, m, nb)
+    x = _img(n, 1)
+    xs = to_gpu(x, dt)
+    x_dev = to_np(xs)   # the exact values the GPU sees
+    b = to_np(g.project(xs))
+    assert rel(b, W @ x_dev.ravel()) <= TOL[f64]
+    y = np.random.default_rng(2).standard_normal((m, nb))
+    ys = to_gpu(y, dt)
+    y_dev = to_np(ys)
+    bt = to_np(g.backproject(ys))
+    assert rel(bt, W.T @ y_dev.ravel()) <= TOL[f64]
+    # adjoint identity with the GPU operators themselves
+    lhs = float(np.dot(b.ravel(), y_dev.ravel()))
+    rhs = float(np.dot(x_dev.ravel(), bt.ravel()))
+    assert abs(lhs - rhs) <= (1e-12 if f64 else 2e-6) * abs(lhs)
+    # packet diagonal and WMG apply
+    L = lv - 1
+    d_ref = oracle_d(n, m, nb, L)
+    d = g.packet_diagonal()
+    scale = np.abs(d_ref).max()
+    assert np.abs(d - d_ref).max() <= TOL[f64] * 10 * scale
+    for lam in (0.0, 0.37):
+        z = to_np(g.wmg_apply(xs, lam=lam))
+        z_ref = wmg.apply_additive_diag(x_dev, d_ref + lam, L)
+        assert rel(z, z_ref) <= TOL[f64] * 10
+
+
+def test_project_ct512_full():
+    n, m, nb, lv = 512, 360, 725, 3
+    print_case("ct512 operators")
+    g = reco.Geometry(n, m, nb, lv, reco.F32)
+    W = oracle_W(n, m, nb)
+    import inputs
+    x = inputs.ellipse_phantom(n, 20, 1000)
+    xs = to_gpu(x, torch.float32)
+    b = to_np(g.project(xs))
+    assert rel(b, W @ x.ravel()) <= 1e-5
+    y = np.random.default_rng(3).standard_normal((m, nb))
+    ys = to_gpu(y, torch.float32)
+    y_dev = to_np(ys)
+    assert rel(to_np(g.backproject(ys)), W.T @ y_dev.ravel()) <= 1e-5
+    assert g.count_nnz() == pytest.approx(W.nnz, rel=1e-4)
+    d_ref = oracle_d(n, m, nb, lv - 1)
+    d = g.packet_diagonal()
+    assert np.abs(d - d_ref).max() <= 1e-5 * np.abs(d_ref).max()
+    z = to_np(g.wmg_apply(xs))
+    assert rel(z, wmg.apply_additive_diag(x, d_ref, lv - 1)) <= 1e-5
+
+
+def test_ct2048_sampled():
+    """2048^2, 2048 angles, 2897 bins at full size: sampled rays, pixels and tiles."""
+    n, m, nb, lv = 2048, 2048, 2897, 5
+    print_case("ct2048 sampled operators")
+    og = OG(n, m, nb)
+    g = reco.Geometry(n, m, nb, lv, reco.F32)
+    import inputs
+    x = inputs.ellipse_phantom(n, 40, 2000)
+    xs = to_gpu(x, torch.float32)
+    b = to_np(g.project(xs)).reshape(m, nb)
+    rng = np.random.default_rng(7)
+    angles = sorted(set([0, 1, m // 4, m // 2, m // 2 + 1, 3 * m // 4, m - 1]
+                        + list(rng.integers(0, m, 9))))
+    for k in angles:
+        bins = np.unique(np.concatenate([[0, nb // 2, nb - 1], rng.integers(0, nb, 24)]))
+        ref = ray_rows(og, int(k), bins) @ x.ravel()
+        got = b[k, bins]
+        assert rel(got, ref) <= 1e-5, k
+    y = rng.standard_normal((m, nb)).astype(np.float32)
+    ys = to_gpu(y, torch.float32)
+    bt = to_np(g.backproject(ys)).ravel()
+    y64 = y.astype(np.float64).ravel()
+    for pix in [0, n - 1, n * n - 1, (n // 2) * n + n // 2] + list(rng.integers(0, n * n, 4)):
+        col = pixel_column(og, int(pix))
+        ref = col @ y64
+        # rounding bound: 1e-5 of the sum of |terms|
+        assert abs(bt[pix] - ref) <= 1e-5 * (np.abs(col) @ np.abs(y64)), pix
