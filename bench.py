@@ -26,9 +26,10 @@ sys.path.insert(0, ROOT)
 PEAK_VALU_LANE_OPS = 256 * 4 * 16 * 2.4e9   # 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz (non-packed)
 HBM_PEAK_GBS = 8000.0
 WORKLOAD = dict(n=512, m=360, nb=725, levels=3, ellipses=20, noise=0.01, seed=1000, tol=1e-3)
-# VALU instructions per inner-loop step of each projector (counted from the gfx950
-# assembly of the float kernels) and the steps per update (rows per nonzero).
-KERNEL_OPS = {"forward": 10.0, "backward": 10.0}
+# Algorithmic VALU lane-operations per nonzero update of A or A^T: evaluate the
+# exact-length weight (one fused multiply-add and one clamp), accumulate it
+# (one fused multiply-add) and advance the ray or pixel position (one add).
+ALG_OPS_PER_UPDATE = 4.0
 
 
 def parse():
@@ -162,7 +163,7 @@ def main():
     dom = "forward" if kt["forward"][1] >= kt["backward"][1] else "backward"
     # the solver launches the projector once per iteration on the current direction
     gups = {k: nnz / (avg_ms[k] * 1e-3) / 1e9 for k in ("forward", "backward") if avg_ms[k] > 0}
-    peak = {k: PEAK_VALU_LANE_OPS / KERNEL_OPS[k] / 1e9 for k in ("forward", "backward")}
+    peak = {k: PEAK_VALU_LANE_OPS / ALG_OPS_PER_UPDATE / 1e9 for k in ("forward", "backward")}
     N, M = w["n"] ** 2, w["m"] * w["nb"]
     spmv_bytes = 8.0 * nnz + 4.0 * (N + M)
     src = {"forward": "project.hip", "backward": "backproject.hip"}[dom]
@@ -177,7 +178,7 @@ def main():
         "avg_launch_ms": round(avg_ms[dom], 5),
         "launches": kt[dom][0],
         "updates_per_launch": nnz,
-        "valu_ops_per_update_assumed": KERNEL_OPS[dom],
+        "alg_valu_ops_per_update": ALG_OPS_PER_UPDATE,
     }
     result = {
         "metric": "WMG-CGLS recons/s at rel-res 1e-3; A/AT Gupdates/s; p50/p99 latency",

@@ -1,8 +1,12 @@
 // Backprojector s = W^T r (Section 2.1), pixel driven, no atomics.
 //
-// A block owns a 16 x 16 pixel tile and loops over the angles in chunks of 32.
-// For each angle of a chunk the tile's detector footprint (at most 24 bins for
-// a 16-pixel tile) is staged in LDS; every pixel then reads its two candidate
+// A block owns a 16 x 16 pixel tile; it holds several angle groups of two
+// waves (two pixels per thread), each looping over its share of the angle
+// chunks (32 angles each); their partial sums are added in group order at the
+// end (no atomics).  For each angle of a chunk the tile's
+// detector footprint (at most 24 bins for a 16-pixel tile) is staged in LDS,
+// double buffered: the next chunk's window is fetched into registers while the
+// current one is consumed.  Every pixel then reads its two candidate
 // bins floor(J) and floor(J)+1, J being the bin coordinate of the pixel
 // centre, and weights them with the same exact intersection length w(t) the
 // forward projector uses (trapezoid in the ray offset t), so the result is the
@@ -15,10 +19,12 @@ namespace reco {
 
 namespace {
 
-constexpr int kTile = 16;
-constexpr int kChunk = 32;   // angles per LDS stage
-constexpr int kWin = 32;     // bins staged per angle
-constexpr int kHalf = 12;    // window starts kHalf bins below the tile centre
+constexpr int kTile = 16;    // pixels per tile side
+constexpr int kThreads = 128; // two pixels per thread: rows ty and ty + 8
+constexpr int kChunk = 32;    // angles per LDS stage
+constexpr int kWin = 32;      // bins staged per angle
+constexpr int kHalf = 12;     // window starts kHalf bins below the tile centre
+constexpr int kPerThread = kChunk * kWin / kThreads;
 
 template <typename T>
 struct BwdK {
@@ -36,112 +42,197 @@ struct BwdK {
   double sa, sx, sf; // out = sa*(W^T r) + sx*xin + sf*fin
 };
 
+// Per-angle constants staged in LDS for the current chunk.
 template <typename T>
-struct BC;
-template <>
-struct BC<float> {
-  float c, s, B, C0, C1, Wm;
-  __device__ BC(const BwdAngle& a) : c(a.cf), s(a.sf), B(a.Bf), C0(a.C0f), C1(a.C1f), Wm(a.Wmaxf) {}
-};
-template <>
-struct BC<double> {
-  double c, s, B, C0, C1, Wm;
-  __device__ BC(const BwdAngle& a) : c(a.c), s(a.s), B(a.B), C0(a.C0), C1(a.C1), Wm(a.Wmax) {}
+struct Meta {
+  T base;   // bin coordinate of the tile centre minus the window start
+  T c, s;   // direction cosines
+  T B, C0, C1, Wm;  // weight: w0 = clamp(C0 - f B), w1 = clamp(C1 + f B), in [0, Wm]
+  int jw;   // first bin of the window
 };
 
+template <typename T>
+__device__ __forceinline__ void fill_meta(Meta<T>& M, const BwdAngle& A, double Xc, double Yc,
+                                          double hb) {
+  const double Jc = fma(Xc, A.c, fma(Yc, A.s, hb));
+  const double fl = floor(Jc);
+  M.jw = (int)fl - kHalf;
+  M.base = (T)((Jc - fl) + kHalf);
+  if constexpr (sizeof(T) == 4) {
+    M.c = A.cf; M.s = A.sf; M.B = A.Bf; M.C0 = A.C0f; M.C1 = A.C1f; M.Wm = A.Wmaxf;
+  } else {
+    M.c = A.c; M.s = A.s; M.B = A.B; M.C0 = A.C0; M.C1 = A.C1; M.Wm = A.Wmax;
+  }
+}
+
+__device__ __forceinline__ float clampw(float v, float hi) { return __builtin_amdgcn_fmed3f(v, 0.0f, hi); }
+__device__ __forceinline__ double clampw(double v, double hi) { return fmin(fmax(v, 0.0), hi); }
+
+// One pixel, one angle: the two candidate bins floor(J), floor(J)+1 of the window.
+template <typename T>
+__device__ __forceinline__ T pixel_term(T J, const T* __restrict__ w, const Meta<T>& M) {
+  const int j0 = (int)J;   // J > 0 inside the window: truncation is floor
+  T f;
+  if constexpr (sizeof(T) == 4) f = __builtin_amdgcn_fractf(J);
+  else f = J - floor(J);
+  const T r0 = w[j0], r1 = w[j0 + 1];
+  const T w0 = clampw(fma(f, -M.B, M.C0), M.Wm);
+  const T w1 = clampw(fma(f, M.B, M.C1), M.Wm);
+  return fma(w0, r0, w1 * r1);
+}
+
+// Angle groups per block: group g handles the chunks c = g, g + G, ...; the G
+// partial sums of a pixel are added in group order at the end.
+template <typename T>
+constexpr int kGroups = sizeof(T) == 4 ? 4 : 2;
+
 template <typename T, int MODE>
-__global__ __launch_bounds__(256) void k_backward(BwdK<T> a) {
+__global__ __launch_bounds__(kThreads * kGroups<T>) void k_backward(BwdK<T> a) {
+  constexpr int G = kGroups<T>;
   if (a.st && a.st->done) return;   // solver finished: later launches are no-ops
-  __shared__ T win[kChunk * kWin];
-  __shared__ T sbase[kChunk];
-  __shared__ int sjw[kChunk];
-  const int tx = threadIdx.x & (kTile - 1), ty = threadIdx.x / kTile;
-  const int ix = blockIdx.x * kTile + tx, iy = blockIdx.y * kTile + ty;
+  __shared__ T win[G][2][kChunk * kWin];
+  __shared__ Meta<T> meta[G][2][kChunk];
+  __shared__ T part[G][2][kThreads];
+  const int grp = __builtin_amdgcn_readfirstlane((int)threadIdx.x / kThreads);
+  const int t = threadIdx.x - grp * kThreads;
+  const int tx = t & (kTile - 1), ty = t / kTile;          // ty in [0, 8)
+  const int ix = blockIdx.x * kTile + tx;
+  const int iy0 = blockIdx.y * kTile + ty, iy1 = iy0 + 8;
   const int n = a.n, nb = a.nb, m = a.m;
   const double hc = 0.5 * (n - 1), hb = 0.5 * (nb - 1);
   const double Xc = blockIdx.x * kTile + 0.5 * (kTile - 1) - hc;
   const double Yc = blockIdx.y * kTile + 0.5 * (kTile - 1) - hc;
   const T dX = T(tx) - T(0.5 * (kTile - 1)), dY = T(ty) - T(0.5 * (kTile - 1));
-  T acc = T(0);
-  for (int k0 = 0; k0 < m; k0 += kChunk) {
-    const int kc = min(kChunk, m - k0);
+  T acc0 = T(0), acc1 = T(0);
+  const int nchunks = (m + kChunk - 1) / kChunk;
+  const int steps = (nchunks + G - 1) / G;     // chunk steps, equal for every group
+  // prologue: this group's first chunk straight into LDS
+  {
+    const int k0 = grp * kChunk;
+    if (t < kChunk && k0 + t < m) fill_meta<T>(meta[grp][0][t], a.ang[k0 + t], Xc, Yc, hb);
     __syncthreads();
-    if ((int)threadIdx.x < kc) {
-      const BwdAngle A = a.ang[k0 + threadIdx.x];
-      const double Jc = fma(Xc, A.c, fma(Yc, A.s, hb));
-      const double fl = floor(Jc);
-      sjw[threadIdx.x] = (int)fl - kHalf;
-      sbase[threadIdx.x] = (T)((Jc - fl) + kHalf);
+#pragma unroll
+    for (int i = 0; i < kPerThread; ++i) {
+      const int e = t + kThreads * i, kk = e / kWin, jj = e % kWin;
+      T v = T(0);
+      if (k0 + kk < m) {
+        const int j = meta[grp][0][kk].jw + jj;
+        if (j >= 0 && j < nb) v = a.sino[(size_t)(k0 + kk) * nb + j];
+      }
+      win[grp][0][e] = v;
     }
     __syncthreads();
-    for (int e = threadIdx.x; e < kc * kWin; e += 256) {
-      const int kk = e / kWin, jj = e % kWin;
-      const int j = sjw[kk] + jj;
-      win[e] = (j >= 0 && j < nb) ? a.sino[(size_t)(k0 + kk) * nb + j] : T(0);
-    }
+  }
+  for (int st = 0; st < steps; ++st) {
+    const int cur = st & 1, nxt = cur ^ 1;
+    const int c = st * G + grp;                  // this group's chunk
+    const int k0 = c * kChunk, kc = max(0, min(kChunk, m - k0));
+    const int k1 = k0 + G * kChunk;              // its next chunk
+    const bool more = st + 1 < steps;
+    // stage the next chunk's constants, then start its window loads
+    if (more && t < kChunk && k1 + t < m) fill_meta<T>(meta[grp][nxt][t], a.ang[k1 + t], Xc, Yc, hb);
     __syncthreads();
+    T pre[kPerThread];
+    if (more) {
+#pragma unroll
+      for (int i = 0; i < kPerThread; ++i) {
+        const int e = t + kThreads * i, kk = e / kWin, jj = e % kWin;
+        pre[i] = T(0);
+        if (k1 + kk < m) {
+          const int j = meta[grp][nxt][kk].jw + jj;
+          if (j >= 0 && j < nb) pre[i] = a.sino[(size_t)(k1 + kk) * nb + j];
+        }
+      }
+    }
+    // compute the current chunk
+#pragma unroll 4
     for (int kk = 0; kk < kc; ++kk) {
-      const BC<T> A(a.ang[k0 + kk]);
-      const T J = fma(dX, A.c, fma(dY, A.s, sbase[kk]));
-      const T fl = floor(J);
-      const int j0 = (int)fl;
-      const T f = J - fl;
-      const T* wp = win + kk * kWin + j0;
-      const T r0 = wp[0], r1 = wp[1];
-      const T w0 = clamp01<T>(fma(f, -A.B, A.C0), A.Wm);
-      const T w1 = clamp01<T>(fma(f, A.B, A.C1), A.Wm);
-      acc = fma(w0, r0, acc);
-      acc = fma(w1, r1, acc);
+      const Meta<T> M = meta[grp][cur][kk];
+      const T* w = win[grp][cur] + kk * kWin;
+      const T Ja = fma(dX, M.c, fma(dY, M.s, M.base));
+      const T Jb = fma(T(8), M.s, Ja);
+      acc0 += pixel_term<T>(Ja, w, M);
+      acc1 += pixel_term<T>(Jb, w, M);
+    }
+    if (more) {
+#pragma unroll
+      for (int i = 0; i < kPerThread; ++i) win[grp][nxt][t + kThreads * i] = pre[i];
+    }
+    __syncthreads();
+  }
+  part[grp][0][t] = acc0;
+  part[grp][1][t] = acc1;
+  __syncthreads();
+  double bp[2] = {0.0, 0.0};
+  if (grp == 0) {
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      T v = part[0][q][t];
+#pragma unroll
+      for (int g2 = 1; g2 < G; ++g2) v += part[g2][q][t];
+      bp[q] = a.h * (double)v;
     }
   }
-  const bool inside = ix < n && iy < n;
-  const size_t p = (size_t)iy * n + ix;
-  const double bp = a.h * (double)acc;
-  if constexpr (MODE == BWD_PLAIN) {
-    if (inside) a.out[p] = (T)bp;
-  } else if constexpr (MODE == BWD_CGLS) {
-    // s = W^T r - lambda x
-    if (inside) a.out[p] = (T)(bp - a.st->lambda * (double)a.xin[p]);
-  } else if constexpr (MODE == BWD_AXPY) {
-    if (inside) {
-      double v = a.sa * bp;
-      if (a.sx != 0.0) v += a.sx * (double)a.xin[(size_t)iy * a.x_ld + ix + a.x_off];
-      if (a.sf != 0.0) v += a.sf * (double)a.fin[p];
-      a.out[p] = (T)v;
+  const int iys[2] = {iy0, iy1};
+  if constexpr (MODE == BWD_SIRT) {
+    double usq = 0.0;
+    if (grp == 0) {
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        if (ix < n && iys[q] < n) {
+          const size_t p = (size_t)iys[q] * n + ix;
+          double u = (double)a.C[p] * bp[q];
+          const T xn = (T)((double)a.out[p] + u);
+          u = (double)xn - (double)a.out[p];
+          a.out[p] = xn;
+          usq += u * u;
+        }
+      }
     }
-  } else if constexpr (MODE == BWD_SIRT) {
     // x += C W^T r, with r = R (b - W x) from the forward pass
-    double u = 0.0;
-    if (inside) {
-      u = (double)a.C[p] * bp;
-      const T xn = (T)((double)a.out[p] + u);
-      u = (double)xn - (double)a.out[p];
-      a.out[p] = xn;
+    double v[1] = {usq};
+    SolverState* sst = a.st;
+    reduce_and_finish<1, kThreads * G / 64>(
+        v, a.red, gridDim.x * gridDim.y, blockIdx.y * gridDim.x + blockIdx.x,
+        [sst](double (&tot)[1]) {
+          const double nrm = sqrt(tot[0]);
+          if (!sst->init) {
+            sst->s0 = nrm;
+            sst->init = 1;
+            if (nrm == 0.0) {   // b = 0: x = 0 is exact, no iteration
+              sst->relres = 0.0;
+              sst->done = 1;
+              return;
+            }
+          }
+          sst->iter += 1;
+          const double rr = sst->s0 > 0.0 ? nrm / sst->s0 : 0.0;
+          sst->relres = rr;
+          if (sst->hist && sst->iter <= sst->hist_cap) sst->hist[sst->iter - 1] = rr;
+          if (!finite(nrm)) sst->done = 3;
+          else if (sst->s0 == 0.0) sst->done = 1;
+          else if (sst->fixed) { if (sst->iter >= sst->max_iter) sst->done = 1; }
+          else if (rr <= sst->tol) sst->done = 1;
+          else if (sst->iter >= sst->max_iter) sst->done = 2;
+        });
+  } else if (grp == 0) {
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int iy = iys[q];
+      if (ix >= n || iy >= n) continue;
+      const size_t p = (size_t)iy * n + ix;
+      if constexpr (MODE == BWD_PLAIN) {
+        a.out[p] = (T)bp[q];
+      } else if constexpr (MODE == BWD_CGLS) {
+        // s = W^T r - lambda x
+        a.out[p] = (T)(bp[q] - a.st->lambda * (double)a.xin[p]);
+      } else if constexpr (MODE == BWD_AXPY) {
+        double v = a.sa * bp[q];
+        if (a.sx != 0.0) v += a.sx * (double)a.xin[(size_t)iy * a.x_ld + ix + a.x_off];
+        if (a.sf != 0.0) v += a.sf * (double)a.fin[p];
+        a.out[p] = (T)v;
+      }
     }
-    double v[1] = {u * u};
-    SolverState* st = a.st;
-    reduce_and_finish<1>(v, a.red, gridDim.x * gridDim.y, blockIdx.y * gridDim.x + blockIdx.x,
-                         [st](double (&tot)[1]) {
-                           const double nrm = sqrt(tot[0]);
-                           if (!st->init) {
-                             st->s0 = nrm;
-                             st->init = 1;
-                             if (nrm == 0.0) {   // b = 0: x = 0 is exact, no iteration
-                               st->relres = 0.0;
-                               st->done = 1;
-                               return;
-                             }
-                           }
-                           st->iter += 1;
-                           const double rr = st->s0 > 0.0 ? nrm / st->s0 : 0.0;
-                           st->relres = rr;
-                           if (st->hist && st->iter <= st->hist_cap) st->hist[st->iter - 1] = rr;
-                           if (!finite(nrm)) st->done = 3;
-                           else if (st->s0 == 0.0) st->done = 1;
-                           else if (st->fixed) { if (st->iter >= st->max_iter) st->done = 1; }
-                           else if (rr <= st->tol) st->done = 1;
-                           else if (st->iter >= st->max_iter) st->done = 2;
-                         });
   }
 }
 
@@ -166,12 +257,13 @@ void bwd_dispatch(const Geometry& g, BwdMode mode, const BwdArgs& a, hipStream_t
   k.sx = a.sx;
   k.sf = a.sf;
   dim3 grid((g.n + kTile - 1) / kTile, (g.n + kTile - 1) / kTile);
+  const dim3 block(kThreads * kGroups<T>);
   TimedLaunch tl(TK_BACKWARD, st);
   switch (mode) {
-    case BWD_PLAIN: hipLaunchKernelGGL((k_backward<T, BWD_PLAIN>), grid, dim3(256), 0, st, k); break;
-    case BWD_CGLS: hipLaunchKernelGGL((k_backward<T, BWD_CGLS>), grid, dim3(256), 0, st, k); break;
-    case BWD_SIRT: hipLaunchKernelGGL((k_backward<T, BWD_SIRT>), grid, dim3(256), 0, st, k); break;
-    case BWD_AXPY: hipLaunchKernelGGL((k_backward<T, BWD_AXPY>), grid, dim3(256), 0, st, k); break;
+    case BWD_PLAIN: hipLaunchKernelGGL((k_backward<T, BWD_PLAIN>), grid, block, 0, st, k); break;
+    case BWD_CGLS: hipLaunchKernelGGL((k_backward<T, BWD_CGLS>), grid, block, 0, st, k); break;
+    case BWD_SIRT: hipLaunchKernelGGL((k_backward<T, BWD_SIRT>), grid, block, 0, st, k); break;
+    case BWD_AXPY: hipLaunchKernelGGL((k_backward<T, BWD_AXPY>), grid, block, 0, st, k); break;
   }
   HIP_CHECK(hipGetLastError());
 }

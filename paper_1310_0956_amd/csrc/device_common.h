@@ -30,10 +30,10 @@ __device__ __forceinline__ int wave_max(int v) {
   return v;
 }
 
-// Sum W values over a 256-thread block in a fixed order.  Result valid in
-// thread 0.  `sh` must hold 4*W doubles.
-template <int W>
-__device__ __forceinline__ void block_sum256(double (&v)[W], double* sh) {
+// Sum W values over a block of NW waves in a fixed order.  Result valid in
+// thread 0.  `sh` must hold NW*W doubles.
+template <int W, int NW = 4>
+__device__ __forceinline__ void block_sum(double (&v)[W], double* sh) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
   for (int i = 0; i < W; ++i) v[i] = wave_sum(v[i]);
@@ -44,20 +44,30 @@ __device__ __forceinline__ void block_sum256(double (&v)[W], double* sh) {
   __syncthreads();
   if (threadIdx.x == 0) {
 #pragma unroll
-    for (int i = 0; i < W; ++i) v[i] = ((sh[i] + sh[W + i]) + sh[2 * W + i]) + sh[3 * W + i];
+    for (int i = 0; i < W; ++i) {
+      double t = sh[i];
+#pragma unroll
+      for (int w = 1; w < NW; ++w) t += sh[w * W + i];
+      v[i] = t;
+    }
   }
   __syncthreads();
 }
 
+template <int W>
+__device__ __forceinline__ void block_sum256(double (&v)[W], double* sh) {
+  block_sum<W, 4>(v, sh);
+}
+
 // Each block contributes W partial sums; the last block to arrive sums them in
 // block order and calls fin(totals) from thread 0.  Returns nothing; the
-// counter is reset for the next use.  Block size must be 256.
-template <int W, typename F>
+// counter is reset for the next use.  Blocks have NW waves.
+template <int W, int NW = 4, typename F>
 __device__ __forceinline__ void reduce_and_finish(double (&v)[W], const RedScratch& red,
                                                   int nblocks, int block_id, F fin) {
-  __shared__ double sh[4 * W];
+  __shared__ double sh[NW * W];
   __shared__ int am_last;
-  block_sum256<W>(v, sh);
+  block_sum<W, NW>(v, sh);
   if (threadIdx.x == 0) {
 #pragma unroll
     for (int i = 0; i < W; ++i) red.partial[(size_t)block_id * W + i] = v[i];
@@ -71,13 +81,13 @@ __device__ __forceinline__ void reduce_and_finish(double (&v)[W], const RedScrat
   double acc[W];
 #pragma unroll
   for (int i = 0; i < W; ++i) acc[i] = 0.0;
-  for (int b = threadIdx.x; b < nblocks; b += 256) {
+  for (int b = threadIdx.x; b < nblocks; b += NW * 64) {
 #pragma unroll
     for (int i = 0; i < W; ++i)
       acc[i] += __hip_atomic_load(&red.partial[(size_t)b * W + i], __ATOMIC_RELAXED,
                                   __HIP_MEMORY_SCOPE_AGENT);
   }
-  block_sum256<W>(acc, sh);
+  block_sum<W, NW>(acc, sh);
   if (threadIdx.x == 0) {
     fin(acc);
     *red.counter = 0u;

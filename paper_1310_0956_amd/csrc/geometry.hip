@@ -78,6 +78,7 @@ void build_angle_tables(Geometry& g) {
 Geometry::~Geometry() {
   auto f = [](void* p) { if (p) (void)hipFree(p); };
   f(d_fwd);
+  f(d_groups);
   f(d_bwd);
   f(d_diag64);
   f(d_diag);
@@ -106,13 +107,28 @@ Geometry* create_geometry(const reco_geometry_desc& d, hipStream_t st) {
   g->nb = d.n_bins;
   g->L = L;
   g->T = 1 << L;
-  g->ld = d.n + 4;
+  g->ld = d.n + 2 * kPad;
   g->h = 2.0 / d.n;
   g->f64 = d.dtype == RECO_F64;
   HIP_CHECK(hipGetDevice(&g->device));
   build_angle_tables(*g);
   HIP_CHECK(hipMalloc(&g->d_fwd, sizeof(FwdAngle) * g->m));
   HIP_CHECK(hipMalloc(&g->d_bwd, sizeof(BwdAngle) * g->m));
+  // forward angle groups: runs of up to 8 consecutive angles with the same walk axis
+  std::vector<int> groups;
+  for (int k = 0; k < g->m;) {
+    const int major = g->h_fwd[k].major;
+    int cnt = 0;
+    while (k < g->m && cnt < 8 && g->h_fwd[k].major == major) {
+      groups.push_back(k++);
+      ++cnt;
+    }
+    while (cnt++ < 8) groups.push_back(-1);
+  }
+  g->ngroups = (int)groups.size() / 8;
+  HIP_CHECK(hipMalloc(&g->d_groups, sizeof(int) * groups.size()));
+  HIP_CHECK(hipMemcpyAsync(g->d_groups, groups.data(), sizeof(int) * groups.size(),
+                           hipMemcpyHostToDevice, st));
   HIP_CHECK(hipMemcpyAsync(g->d_fwd, g->h_fwd.data(), sizeof(FwdAngle) * g->m,
                            hipMemcpyHostToDevice, st));
   HIP_CHECK(hipMemcpyAsync(g->d_bwd, g->h_bwd.data(), sizeof(BwdAngle) * g->m,

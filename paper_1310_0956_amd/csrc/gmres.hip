@@ -297,7 +297,7 @@ reco_status gmres_impl(Geometry& g, const void* bvoid, void* xvoid, const reco_s
       ba.out = wv;
       ba.x = w.zP;
       ba.x_ld = g.ld;
-      ba.x_off = 2;
+      ba.x_off = kPad;
       ba.sa = 1.0;
       ba.sx = o.lambda;
       ba.st = w.st;

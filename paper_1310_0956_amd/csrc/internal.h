@@ -68,15 +68,21 @@ struct BwdAngle {
 // ---------------------------------------------------------------------------
 struct Workspace;  // solver buffers (solve.hip)
 
+// Zero columns on each side of the padded image copies read by the forward
+// projector (see project.hip).
+constexpr int kPad = 4;
+
 struct Geometry {
   reco_geometry_desc desc{};
   int n = 0, m = 0, nb = 0, L = 0, T = 1;  // L packet levels, T = 2^L
-  int ld = 0;                               // padded row length of image copies
+  int ld = 0;                               // padded row length of image copies (n + 2 kPad)
   double h = 0;
   bool f64 = false;
   int device = 0;
 
   FwdAngle* d_fwd = nullptr;   // [m]
+  int* d_groups = nullptr;     // [ngroups][8] angle groups walked together (forward)
+  int ngroups = 0;
   BwdAngle* d_bwd = nullptr;   // [m]
   std::vector<FwdAngle> h_fwd;
   std::vector<BwdAngle> h_bwd;

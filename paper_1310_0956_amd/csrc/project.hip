@@ -1,19 +1,28 @@
 // Forward projector q = W x (Section 2.1, eq. sys), ray driven, matrix free.
 //
-// One thread per ray; a wave holds 64 consecutive detector bins of one angle,
-// a block 4 consecutive angles.  Each ray is walked along its major axis: at
-// every row (or column, for angles closer to the x axis, via a transposed image
-// copy so that the wave's loads stay contiguous) the ray overlaps exactly two
-// candidate pixels, floor(P) and floor(P)+1, where P is the crossing position
-// in pixel units.  With f = P - floor(P) the exact intersection lengths are
+// Each ray is walked along its major axis: at every row (or column, for angles
+// closer to the x axis, via a transposed image copy) the ray overlaps exactly
+// two candidate pixels, floor(P) and floor(P)+1, where P is the crossing
+// position in pixel units.  With f = P - floor(P) the exact intersection
+// lengths are
 //   w0 = h clamp((1/2 - f) B + C, 0, 1/u),  w1 = h/u - w0,
-// u = |major direction cosine|, B = 1/v, C = 1/(2u), v = |minor cosine|
-// (the trapezoid of the chord length versus offset; the two weights of a row
-// always sum to the row's chord h/u).  Images are read with two zero columns
-// of padding on each side so rays leaving the image need no masking.
+// u = |major direction cosine|, B = 1/v, C = 1/(2u), v = |minor cosine| (the
+// trapezoid of the chord length against the ray offset; the two weights of a
+// row always add up to the row's chord h/u).  Candidate columns are clamped to
+// [-2, n]; the padded image copies carry kPad >= 2 zero columns on each side,
+// so a ray outside the image reads zeros.
 //
-// Positions are walked in 32.32 fixed point (float path) or float64 (double
-// path), so the geometry error stays far below the float weight error.
+// Work decomposition: a block takes up to 8 neighbouring angles that share the
+// walk axis ("group") times 32 neighbouring detector bins, one ray per thread.
+// It walks the rows in bands: the columns the block's rays cross in a band
+// (known from the corner rays, since positions are linear in bin and row) are
+// staged in LDS with coalesced loads, double buffered through registers, and
+// the rays read their two pixels per row from LDS.  A band wider than the LDS
+// window (only for very sparse angle sets) is walked straight from memory.
+//
+// Positions are walked in 32.32 fixed point (float path) or recomputed in
+// float64 (double path), so the geometry error stays far below the float
+// weight error.
 #include "device_common.h"
 #include "timing.h"
 
@@ -21,7 +30,14 @@ namespace reco {
 
 namespace {
 
-constexpr int kFwdWaves = 4;
+constexpr int kSlots = 8;       // angles per block
+constexpr int kBins = 32;       // bins per block
+constexpr int kWinCols = 128;   // staged columns per band
+constexpr int kThreads = kSlots * kBins;
+constexpr int kStageRows = kThreads / kWinCols;   // rows loaded per staging pass
+
+template <typename T>
+constexpr int kBand = sizeof(T) == 4 ? 32 : 16;   // rows per staged band
 
 template <typename T>
 struct FwdK {
@@ -31,6 +47,7 @@ struct FwdK {
   const T* b;
   const T* R;
   const FwdAngle* ang;
+  const int* groups;   // [ngroups][8] angle indices, -1 = empty slot
   SolverState* st;
   RedScratch red;
   unsigned long long* count;
@@ -38,124 +55,293 @@ struct FwdK {
   double h;
 };
 
+constexpr int kBufferFlags = 0x00020000;   // raw 32-bit dword access (gfx9 family)
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t image_rsrc(const void* img, size_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(img), (short)0, (int)bytes,
+                                           kBufferFlags);
+}
+
+// Buffer loads: offsets past the image read 0.
+__device__ __forceinline__ float load_elem(__amdgpu_buffer_rsrc_t rs, unsigned voff, int soff, float) {
+  return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, voff, soff, 0));
+}
+__device__ __forceinline__ double load_elem(__amdgpu_buffer_rsrc_t rs, unsigned voff, int soff, double) {
+  const auto v = __builtin_amdgcn_raw_buffer_load_b64(rs, voff, soff, 0);
+  const unsigned lo = v[0], hi = v[1];
+  return __hiloint2double((int)hi, (int)lo);
+}
+
+__device__ __forceinline__ int iclamp(int v, int lo, int hi) { return min(max(v, lo), hi); }
+
+// Weight of the left candidate from the fraction (float and double forms).
+__device__ __forceinline__ float left_weight(float f, float B, float C, float Wm) {
+  return __builtin_amdgcn_fmed3f(fmaf(0.5f - f, B, C), 0.0f, Wm);
+}
+__device__ __forceinline__ double left_weight(double f, double B, double C, double Wm) {
+  return fmin(fmax(fma(0.5 - f, B, C), 0.0), Wm);
+}
+
+// Position walker along the rows of one ray.  col() is the column of the left
+// candidate relative to an offset set by shift_cols (the current LDS window).
 template <typename T>
-struct Walker;
+struct Walk;
 
 template <>
-struct Walker<float> {
-  long long p, dp;
-  __device__ void init(double P, const FwdAngle& a) {
-    p = __double2ll_rn(P * 4294967296.0);
-    dp = a.dP;
+struct Walk<float> {
+  unsigned long long p, dp;   // 32.32 fixed point
+  __device__ void init(double P, double, long long dP) {
+    p = (unsigned long long)__double2ll_rn(P * 4294967296.0);
+    dp = (unsigned long long)dP;
   }
-  __device__ int idx() const { return (int)(p >> 32); }
-  __device__ float frac() const {
-    return (float)(unsigned)(p & 0xffffffffll) * 2.3283064365386963e-10f;
+  __device__ __forceinline__ int col() const { return (int)(p >> 32); }
+  __device__ __forceinline__ float frac() const {
+    return (float)(unsigned)(p & 0xffffffffull) * 2.3283064365386963e-10f;
   }
-  __device__ void step() { p += dp; }
+  __device__ __forceinline__ void step() { p += dp; }
+  __device__ __forceinline__ void shift_cols(int dc) {
+    p -= (unsigned long long)(long long)dc << 32;
+  }
 };
 
 template <>
-struct Walker<double> {
-  double P0, slope;
-  int r;
-  double cur;
-  __device__ void init(double P, const FwdAngle& a) {
+struct Walk<double> {
+  double P0, slope, cur;
+  int r, off;
+  __device__ void init(double P, double s, long long) {
     P0 = P;
-    slope = a.slope;
-    r = 0;
+    slope = s;
     cur = P;
+    r = 0;
+    off = 0;
   }
-  __device__ int idx() const { return (int)floor(cur); }
-  __device__ double frac() const { return cur - floor(cur); }
-  __device__ void step() {
+  __device__ __forceinline__ int col() const { return (int)floor(cur) - off; }
+  __device__ __forceinline__ double frac() const { return cur - floor(cur); }
+  __device__ __forceinline__ void step() {
     ++r;
     cur = fma((double)r, slope, P0);
   }
+  __device__ __forceinline__ void shift_cols(int dc) { off += dc; }
 };
 
 template <typename T>
-__device__ __forceinline__ T wB(const FwdAngle& a);
-template <>
-__device__ __forceinline__ float wB<float>(const FwdAngle& a) { return a.Bf; }
-template <>
-__device__ __forceinline__ double wB<double>(const FwdAngle& a) { return a.B; }
+__device__ __forceinline__ T wB(const FwdAngle& a) {
+  if constexpr (sizeof(T) == 4) return a.Bf; else return a.B;
+}
 template <typename T>
-__device__ __forceinline__ T wC(const FwdAngle& a);
-template <>
-__device__ __forceinline__ float wC<float>(const FwdAngle& a) { return a.Cf; }
-template <>
-__device__ __forceinline__ double wC<double>(const FwdAngle& a) { return a.C; }
+__device__ __forceinline__ T wC(const FwdAngle& a) {
+  if constexpr (sizeof(T) == 4) return a.Cf; else return a.C;
+}
 template <typename T>
-__device__ __forceinline__ T wM(const FwdAngle& a);
-template <>
-__device__ __forceinline__ float wM<float>(const FwdAngle& a) { return a.Wmaxf; }
-template <>
-__device__ __forceinline__ double wM<double>(const FwdAngle& a) { return a.Wmax; }
+__device__ __forceinline__ T wM(const FwdAngle& a) {
+  if constexpr (sizeof(T) == 4) return a.Wmaxf; else return a.Wmax;
+}
+
+// `rows` rows of one ray read from an LDS window (row stride kWinCols).  The
+// window-relative column is clamped into [lo_w, hi_w]: the window images of
+// image columns -2 and n, intersected with the loaded part of the window.
+template <typename T>
+__device__ __forceinline__ void band_lds(const T* __restrict__ w, Walk<T>& wk, int rows, int lo_w,
+                                         int hi_w, T B, T C, T Wm, T& acc0, T& acc1) {
+  int r = 0;
+  for (; r + 3 < rows; r += 4) {
+    T w0[4], x0[4], x1[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int c = iclamp(wk.col(), lo_w, hi_w);
+      const T* q = w + (r + u) * kWinCols + c;
+      x0[u] = q[0];
+      x1[u] = q[1];
+      w0[u] = left_weight(wk.frac(), B, C, Wm);
+      wk.step();
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      acc0 = fma(w0[u], x0[u] - x1[u], acc0);
+      acc1 += x1[u];
+    }
+  }
+  for (; r < rows; ++r) {
+    const int c = iclamp(wk.col(), lo_w, hi_w);
+    const T* q = w + r * kWinCols + c;
+    const T x0 = q[0], x1 = q[1];
+    acc0 = fma(left_weight(wk.frac(), B, C, Wm), x0 - x1, acc0);
+    acc1 += x1;
+    wk.step();
+  }
+}
+
+// `rows` rows of one ray read straight from the padded image (bands wider than
+// the LDS window).  The walker's column is relative to image column c0.
+template <typename T>
+__device__ __forceinline__ void band_mem(__amdgpu_buffer_rsrc_t rs, int ld, int n, int r0, int rows,
+                                         int c0, Walk<T>& wk, T B, T C, T Wm, T& acc0, T& acc1) {
+  for (int r = 0; r < rows; ++r) {
+    const int c = iclamp(wk.col() + c0, -2, n) + kPad;
+    const int soff = (r0 + r) * ld * (int)sizeof(T);
+    const T x0 = load_elem(rs, (unsigned)c * sizeof(T), soff, T(0));
+    const T x1 = load_elem(rs, (unsigned)(c + 1) * sizeof(T), soff, T(0));
+    acc0 = fma(left_weight(wk.frac(), B, C, Wm), x0 - x1, acc0);
+    acc1 += x1;
+    wk.step();
+  }
+}
+
+// Column window [c0, c1] of band rows [rb, re]: the floor(P) range over the
+// block's corner rays (first and last bin of each angle at the band's first and
+// last row), widened by one column on each side for rounding and clamped to
+// [-2, n+1].  Every wave computes it redundantly (one corner per lane), so no
+// block synchronisation is needed.
+struct Window {
+  int c0, c1;
+};
+
+__device__ __forceinline__ Window band_window(const FwdAngle& ca, bool cvalid, int cj, bool cfirst,
+                                              int rb, int re, int n) {
+  int lo = 1 << 30, hi = -(1 << 30);
+  if (cvalid) {
+    const int r = cfirst ? rb : re;
+    const double P = fma((double)r, ca.slope, fma((double)cj, ca.inv, ca.A0));
+    const int f = (int)fmin(fmax(floor(P), -1.0e9), 1.0e9);
+    lo = f - 1;
+    hi = f + 1;
+  }
+  Window w;
+  w.c0 = iclamp(__builtin_amdgcn_readfirstlane(wave_min(lo)), -2, n);
+  w.c1 = iclamp(__builtin_amdgcn_readfirstlane(wave_max(hi)), -2, n) + 1;
+  return w;
+}
 
 template <typename T, int MODE>
-__global__ __launch_bounds__(256) void k_forward(FwdK<T> a) {
+__global__ __launch_bounds__(kThreads) void k_forward(FwdK<T> a) {
+  constexpr int BAND = kBand<T>;
+  constexpr int STAGE_PER = BAND / kStageRows;   // loads per thread per band
   if (a.st && a.st->done) return;   // solver finished: later launches are no-ops
-  const int lane = threadIdx.x & 63;
-  const int k = blockIdx.y * kFwdWaves + (threadIdx.x >> 6);
-  const int j = blockIdx.x * 64 + lane;
-  const int n = a.n;
-  const bool valid = (k < a.m) && (j < a.nb);
-  T result = T(0);
-  unsigned long long cnt = 0;
-  if (k < a.m) {
-    const FwdAngle ang = a.ang[k];
-    const T* __restrict__ img = ang.major ? a.imgTP : a.imgP;
-    const double P0 = fma((double)j, ang.inv, ang.A0);
-    int lo = n, hi = -1;
-    if (valid) {
-      if (ang.slope == 0.0) {
-        if (P0 >= -1.5 && P0 <= n + 0.5) { lo = 0; hi = n - 1; }
-      } else {
-        const double t1 = (-1.5 - P0) / ang.slope, t2 = (n + 0.5 - P0) / ang.slope;
-        const double tl = fmin(t1, t2), th = fmax(t1, t2);
-        lo = (int)fmin(fmax(0.0, ceil(tl)), (double)n);
-        hi = (int)fmax(fmin((double)(n - 1), floor(th)), -1.0);
-      }
+  __shared__ T win[2][BAND * kWinCols];
+  __shared__ int sh_lo[kThreads / 64], sh_hi[kThreads / 64];
+  const int t = threadIdx.x;
+  const int lane = t & 63, wv = t >> 6;
+  const int n = a.n, nb = a.nb;
+  const int g = blockIdx.y;
+  const int jfirst = blockIdx.x * kBins;
+  const int jlast = min(jfirst + kBins - 1, nb - 1);
+  const int k0 = a.groups[g * kSlots];            // first angle: sets the walk axis
+  const int kl = a.groups[g * kSlots + (t >> 5)];
+  const int jown = jfirst + (t & 31);
+  const bool valid = kl >= 0 && jown <= jlast;
+  // invalid lanes shadow the block's first ray so that they stay in the window
+  const int k = valid ? kl : k0;
+  const int j = valid ? jown : jfirst;
+  const FwdAngle ang = a.ang[k];
+  const FwdAngle ang0 = a.ang[k0];
+  const T* img = ang0.major ? a.imgTP : a.imgP;
+  const __amdgpu_buffer_rsrc_t rs = image_rsrc(img, (size_t)n * a.ld * sizeof(T));
+  const double P0 = fma((double)j, ang.inv, ang.A0);
+  // rows where this ray touches the image (with margin); block union
+  int lo = n, hi = -1;
+  if (valid) {
+    if (ang.slope == 0.0) {
+      if (P0 >= -1.5 && P0 <= n + 0.5) { lo = 0; hi = n - 1; }
+    } else {
+      const double t1 = (-1.5 - P0) / ang.slope, t2 = (n + 0.5 - P0) / ang.slope;
+      const double tl = fmin(t1, t2), th = fmax(t1, t2);
+      lo = (int)fmin(fmax(0.0, ceil(tl)), (double)n);
+      hi = (int)fmax(fmin((double)(n - 1), floor(th)), -1.0);
     }
-    lo = wave_min(lo);
-    hi = wave_max(hi);
-    const T B = wB<T>(ang), C = wC<T>(ang), Wm = wM<T>(ang);
-    T acc0 = T(0), acc1 = T(0);
-    if (lo <= hi) {
-      Walker<T> w;
-      w.init(fma((double)lo, ang.slope, P0), ang);
-      const T* __restrict__ row = img + (size_t)lo * a.ld + 2;
-      for (int r = lo; r <= hi; ++r) {
-        const int i0 = min(max(w.idx(), -2), n);
-        const T f = w.frac();
-        const T w0 = clamp01<T>(fma(T(0.5) - f, B, C), Wm);
-        if constexpr (MODE == FWD_COUNT) {
-          const T w1 = Wm - w0;
-          const T eps = T(1e-9) * Wm;
-          cnt += (w0 > eps && i0 >= 0 && i0 < n) ? 1 : 0;
-          cnt += (w1 > eps && i0 + 1 >= 0 && i0 + 1 < n) ? 1 : 0;
-        } else {
-          const T x0 = row[i0], x1 = row[i0 + 1];
-          acc0 = fma(w0, x0 - x1, acc0);
-          acc1 += x1;
-        }
-        w.step();
-        row += a.ld;
-      }
-    }
-    result = (T)a.h * fma(Wm, acc1, acc0);
   }
-  const size_t i = (size_t)k * a.nb + j;
+  lo = wave_min(lo);
+  hi = wave_max(hi);
+  if (lane == 0) {
+    sh_lo[wv] = lo;
+    sh_hi[wv] = hi;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < kThreads / 64; ++i) {
+    lo = min(lo, sh_lo[i]);
+    hi = max(hi, sh_hi[i]);
+  }
+  lo = __builtin_amdgcn_readfirstlane(lo);
+  hi = __builtin_amdgcn_readfirstlane(hi);
+  // the corner ray this lane evaluates for the band windows
+  const int cc = lane & 31;
+  const int ck = a.groups[g * kSlots + (cc >> 2)];
+  const bool cvalid = ck >= 0;
+  const FwdAngle ca = a.ang[cvalid ? ck : k0];
+  const int cj = ((cc >> 1) & 1) ? jlast : jfirst;
+  const bool cfirst = (cc & 1) == 0;
+
+  const T B = wB<T>(ang), C = wC<T>(ang), Wm = wM<T>(ang);
+  T acc0 = T(0), acc1 = T(0);
+  const int nbands = hi >= lo ? (hi - lo + BAND) / BAND : 0;
+  Walk<T> wk;
+  wk.init(fma((double)lo, ang.slope, P0), ang.slope, ang.dP);
+  // staging: thread loads column (t % kWinCols) of rows (t / kWinCols) + kStageRows * i
+  const int scol = t % kWinCols;
+  const int srow = __builtin_amdgcn_readfirstlane(t / kWinCols);   // uniform per wave
+  const int rbytes = a.ld * (int)sizeof(T);
+  Window wcur{0, 0};
+  int cur_shift = 0;   // window start the walker's columns are currently relative to
+  if (nbands > 0) {
+    wcur = band_window(ca, cvalid, cj, cfirst, lo, min(lo + BAND - 1, hi), n);
+    if (wcur.c1 - wcur.c0 + 1 <= kWinCols) {
+#pragma unroll
+      for (int i = 0; i < STAGE_PER; ++i) {
+        const int row = srow + kStageRows * i;
+        T v = T(0);
+        if (scol <= wcur.c1 - wcur.c0)
+          v = load_elem(rs, (unsigned)(wcur.c0 + kPad + scol) * sizeof(T), (lo + row) * rbytes, T(0));
+        win[0][row * kWinCols + scol] = v;
+      }
+    }
+    __syncthreads();
+  }
+  for (int bnd = 0; bnd < nbands; ++bnd) {
+    const int cur = bnd & 1, nxt = cur ^ 1;
+    const int rb = lo + bnd * BAND;
+    const int rows = min(BAND, hi - rb + 1);
+    const bool more = bnd + 1 < nbands;
+    Window wnext{0, 0};
+    T pre[STAGE_PER];
+    bool next_lds = false;
+    if (more) {
+      const int rb2 = rb + BAND;
+      wnext = band_window(ca, cvalid, cj, cfirst, rb2, min(rb2 + BAND - 1, hi), n);
+      next_lds = wnext.c1 - wnext.c0 + 1 <= kWinCols;
+      if (next_lds) {
+#pragma unroll
+        for (int i = 0; i < STAGE_PER; ++i) {
+          const int row = srow + kStageRows * i;
+          pre[i] = T(0);
+          if (scol <= wnext.c1 - wnext.c0)
+            pre[i] = load_elem(rs, (unsigned)(wnext.c0 + kPad + scol) * sizeof(T),
+                               (rb2 + row) * rbytes, T(0));
+        }
+      }
+    }
+    // walker columns relative to this band's window start
+    wk.shift_cols(wcur.c0 - cur_shift);
+    cur_shift = wcur.c0;
+    const int width = wcur.c1 - wcur.c0 + 1;
+    if (width <= kWinCols) {
+      band_lds<T>(win[cur], wk, rows, max(-2 - wcur.c0, 0), min(n - wcur.c0, width - 2), B, C, Wm,
+                  acc0, acc1);
+    } else {
+      band_mem<T>(rs, a.ld, n, rb, rows, wcur.c0, wk, B, C, Wm, acc0, acc1);
+    }
+    if (next_lds) {
+#pragma unroll
+      for (int i = 0; i < STAGE_PER; ++i) win[nxt][(srow + kStageRows * i) * kWinCols + scol] = pre[i];
+    }
+    wcur = wnext;
+    __syncthreads();
+  }
+  const T result = (T)a.h * fma(Wm, acc1, acc0);
+  const size_t i = (size_t)k * nb + j;   // valid lanes only use it
   if constexpr (MODE == FWD_PLAIN) {
     if (valid) a.out[i] = result;
   } else if constexpr (MODE == FWD_SIRT) {
     if (valid) a.out[i] = (T)((double)a.R[i] * ((double)a.b[i] - (double)result));
-  } else if constexpr (MODE == FWD_COUNT) {
-    double v[1] = {(double)cnt};
-    __shared__ double sh[4];
-    block_sum256<1>(v, sh);
-    if (threadIdx.x == 0) atomicAdd(a.count, (unsigned long long)v[0]);
   } else if constexpr (MODE == FWD_CGLS) {
     // q = W z + beta q_old  (q_old = W p_old, so q = W (z + beta p_old) = W p_new)
     double q = 0.0;
@@ -167,24 +353,52 @@ __global__ __launch_bounds__(256) void k_forward(FwdK<T> a) {
     double v[1] = {q * q};
     SolverState* st = a.st;
     const int nblk = gridDim.x * gridDim.y;
-    reduce_and_finish<1>(v, a.red, nblk, blockIdx.y * gridDim.x + blockIdx.x,
-                         [st](double (&tot)[1]) {
-                           const double delta = tot[0] + st->lambda * st->pp;
-                           st->delta = delta;
-                           if (!finite(delta)) {
-                             st->done = 3;
-                             st->alpha = 0.0;
-                           } else if (delta <= 0.0) {
-                             st->done = 1;   // zero direction: nothing left to do
-                             st->alpha = 0.0;
-                           } else {
-                             st->alpha = st->gamma / delta;
-                           }
-                         });
+    reduce_and_finish<1, kThreads / 64>(v, a.red, nblk, blockIdx.y * gridDim.x + blockIdx.x,
+                                        [st](double (&tot)[1]) {
+                                          const double delta = tot[0] + st->lambda * st->pp;
+                                          st->delta = delta;
+                                          if (!finite(delta)) {
+                                            st->done = 3;
+                                            st->alpha = 0.0;
+                                          } else if (delta <= 0.0) {
+                                            st->done = 1;   // zero direction: nothing to do
+                                            st->alpha = 0.0;
+                                          } else {
+                                            st->alpha = st->gamma / delta;
+                                          }
+                                        });
   }
 }
 
-// x[n][n] -> xP[n][ld] (2 zero columns on each side) and its transpose xTP.
+// Nonzero count of W: one thread per ray, every row of the image, float64
+// weights (no image access).
+__global__ __launch_bounds__(256) void k_count(const FwdAngle* __restrict__ angs, int n, int nb,
+                                               int m, unsigned long long* count) {
+  const size_t ray = blockIdx.x * (size_t)256 + threadIdx.x;
+  unsigned long long cnt = 0;
+  if (ray < (size_t)m * nb) {
+    const int k = (int)(ray / nb), j = (int)(ray % nb);
+    const FwdAngle ang = angs[k];
+    const double P0 = fma((double)j, ang.inv, ang.A0);
+    const double eps = 1e-9 * ang.Wmax;
+    for (int r = 0; r < n; ++r) {
+      const double P = fma((double)r, ang.slope, P0);
+      if (P < -2.0 || P > n + 1.0) continue;
+      const double fl = floor(P);
+      const int i0 = (int)fl;
+      const double w0 = fmin(fmax(fma(0.5 - (P - fl), ang.B, ang.C), 0.0), ang.Wmax);
+      const double w1 = ang.Wmax - w0;
+      cnt += (w0 > eps && i0 >= 0 && i0 < n) ? 1 : 0;
+      cnt += (w1 > eps && i0 + 1 >= 0 && i0 + 1 < n) ? 1 : 0;
+    }
+  }
+  double v[1] = {(double)cnt};
+  __shared__ double sh[4];
+  block_sum256<1>(v, sh);
+  if (threadIdx.x == 0) atomicAdd(count, (unsigned long long)v[0]);
+}
+
+// x[n][n] -> xP[n][ld] (kPad zero columns on each side) and its transpose xTP.
 template <typename T>
 __global__ __launch_bounds__(256) void k_pad_transpose(const T* __restrict__ x, T* __restrict__ xP,
                                                        T* __restrict__ xTP, int n, int ld) {
@@ -198,22 +412,19 @@ __global__ __launch_bounds__(256) void k_pad_transpose(const T* __restrict__ x, 
     T v = T(0);
     if (iy < n && ix < n) {
       v = x[(size_t)iy * n + ix];
-      xP[(size_t)iy * ld + ix + 2] = v;
+      xP[(size_t)iy * ld + ix + kPad] = v;
     }
     tile[r][tx] = v;
   }
-  // pad columns
-  if (blockIdx.x == 0 && threadIdx.x < 32) {
-    const int iy = y0 + threadIdx.x;
-    if (iy < n) {
-      xP[(size_t)iy * ld + 0] = T(0);
-      xP[(size_t)iy * ld + 1] = T(0);
-      xP[(size_t)iy * ld + n + 2] = T(0);
-      xP[(size_t)iy * ld + n + 3] = T(0);
-      xTP[(size_t)iy * ld + 0] = T(0);
-      xTP[(size_t)iy * ld + 1] = T(0);
-      xTP[(size_t)iy * ld + n + 2] = T(0);
-      xTP[(size_t)iy * ld + n + 3] = T(0);
+  if (blockIdx.x == 0) {   // zero margins of rows y0..y0+31 of both copies
+    for (int e = threadIdx.x; e < 32 * 2 * kPad; e += 256) {
+      const int r = e / (2 * kPad), c = e % (2 * kPad);
+      const int row = y0 + r;
+      const int col = c < kPad ? c : n + c;   // [0, kPad) and [n+kPad, n+2kPad)
+      if (row < n) {
+        xP[(size_t)row * ld + col] = T(0);
+        xTP[(size_t)row * ld + col] = T(0);
+      }
     }
   }
   __syncthreads();
@@ -221,7 +432,7 @@ __global__ __launch_bounds__(256) void k_pad_transpose(const T* __restrict__ x, 
   for (int i = 0; i < 4; ++i) {
     const int r = ty + 8 * i;
     const int ox = x0 + r, oy = y0 + tx;  // output row = original column
-    if (ox < n && oy < n) xTP[(size_t)ox * ld + oy + 2] = tile[tx][r];
+    if (ox < n && oy < n) xTP[(size_t)ox * ld + oy + kPad] = tile[tx][r];
   }
 }
 
@@ -234,6 +445,7 @@ FwdK<T> make_args(const Geometry& g, const FwdArgs& a) {
   k.b = (const T*)a.b;
   k.R = (const T*)a.R;
   k.ang = g.d_fwd;
+  k.groups = g.d_groups;
   k.st = a.st;
   k.red = a.red;
   k.count = a.count;
@@ -247,23 +459,28 @@ FwdK<T> make_args(const Geometry& g, const FwdArgs& a) {
 
 template <typename T>
 void fwd_dispatch(const Geometry& g, FwdMode mode, const FwdArgs& a, hipStream_t st) {
-  dim3 grid((g.nb + 63) / 64, (g.m + kFwdWaves - 1) / kFwdWaves);
-  FwdK<T> k = make_args<T>(g, a);
   TimedLaunch tl(TK_FORWARD, st);
+  if (mode == FWD_COUNT) {
+    const size_t rays = g.M();
+    hipLaunchKernelGGL(k_count, dim3((unsigned)((rays + 255) / 256)), dim3(256), 0, st, g.d_fwd,
+                       g.n, g.nb, g.m, a.count);
+    HIP_CHECK(hipGetLastError());
+    return;
+  }
+  dim3 grid((g.nb + kBins - 1) / kBins, g.ngroups);
+  FwdK<T> k = make_args<T>(g, a);
   switch (mode) {
-    case FWD_PLAIN: hipLaunchKernelGGL((k_forward<T, FWD_PLAIN>), grid, dim3(256), 0, st, k); break;
-    case FWD_CGLS: hipLaunchKernelGGL((k_forward<T, FWD_CGLS>), grid, dim3(256), 0, st, k); break;
-    case FWD_SIRT: hipLaunchKernelGGL((k_forward<T, FWD_SIRT>), grid, dim3(256), 0, st, k); break;
-    case FWD_COUNT: hipLaunchKernelGGL((k_forward<T, FWD_COUNT>), grid, dim3(256), 0, st, k); break;
+    case FWD_PLAIN: hipLaunchKernelGGL((k_forward<T, FWD_PLAIN>), grid, dim3(kThreads), 0, st, k); break;
+    case FWD_CGLS: hipLaunchKernelGGL((k_forward<T, FWD_CGLS>), grid, dim3(kThreads), 0, st, k); break;
+    case FWD_SIRT: hipLaunchKernelGGL((k_forward<T, FWD_SIRT>), grid, dim3(kThreads), 0, st, k); break;
+    default: break;
   }
   HIP_CHECK(hipGetLastError());
 }
 
 }  // namespace
 
-int forward_blocks(const Geometry& g) {
-  return ((g.nb + 63) / 64) * ((g.m + kFwdWaves - 1) / kFwdWaves);
-}
+int forward_blocks(const Geometry& g) { return ((g.nb + kBins - 1) / kBins) * g.ngroups; }
 
 void launch_forward(const Geometry& g, FwdMode mode, const FwdArgs& a, hipStream_t st) {
   if (g.f64) fwd_dispatch<double>(g, mode, a, st);

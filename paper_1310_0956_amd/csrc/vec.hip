@@ -45,7 +45,7 @@ __global__ __launch_bounds__(256) void k_cgls_update(T* __restrict__ x, T* __res
     const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
     if (i < N) {
       const size_t iy = i / n, ix = i % n;
-      const double z = (double)zP[iy * ld + ix + 2];
+      const double z = (double)zP[iy * ld + ix + kPad];
       const T pn = (T)(z + beta * (double)p[i]);
       p[i] = pn;
       x[i] = (T)((double)x[i] + alpha * (double)pn);

@@ -109,7 +109,7 @@ __global__ __launch_bounds__(256) void k_wmg(WmgK<T> a) {
     zv[i] = tile[r][tx];
     if (iy < n && ix < n) {
       if (a.z) a.z[(size_t)iy * n + ix] = zv[i];
-      if (a.zP) a.zP[(size_t)iy * a.ld + ix + 2] = zv[i];
+      if (a.zP) a.zP[(size_t)iy * a.ld + ix + kPad] = zv[i];
     }
   }
   if (a.zTP) {
@@ -117,7 +117,7 @@ __global__ __launch_bounds__(256) void k_wmg(WmgK<T> a) {
     for (int i = 0; i < 4; ++i) {
       const int r = ty + 8 * i;
       const int ox = x0 + r, oy = y0 + tx;
-      if (ox < n && oy < n) a.zTP[(size_t)ox * a.ld + oy + 2] = tile[tx][r];
+      if (ox < n && oy < n) a.zTP[(size_t)ox * a.ld + oy + kPad] = tile[tx][r];
     }
   }
   if constexpr (MODE == WMG_CGLS || MODE == WMG_CGLS_INIT) {
