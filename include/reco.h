@@ -212,7 +212,9 @@ reco_status reco_poll(reco_server s, uint64_t ticket, reco_solve_info* info,
 /* Per-kernel timing (profiling aid).  While enabled, every launch of a timed
  * kernel family is bracketed by HIP events recorded on its launch stream.
  * Families: 0 forward projector, 1 backprojector, 2 WMG apply, 3 CGLS vector
- * update, 4 packet-diagonal setup, 5 image padding/transposition.
+ * update, 4 packet-diagonal setup, 5 image padding/transposition, 6 one replay
+ * of a batched-iteration graph (reco_solve_batch and the server; the kernels
+ * inside a graph are not timed individually).
  * reco_timing_read waits for the recorded events and returns the number of
  * timed launches and their summed duration in milliseconds since the last
  * reset.  Disabled by default. */

@@ -108,7 +108,8 @@ def clock() -> float:
     return _lib.reco_clock()
 
 
-TIMED = {"forward": 0, "backward": 1, "wmg": 2, "update": 3, "packet_diag": 4, "prep": 5}
+TIMED = {"forward": 0, "backward": 1, "wmg": 2, "update": 3, "packet_diag": 4, "prep": 5,
+         "batch_graph": 6}
 
 
 def timing_enable(on=True):
@@ -267,16 +268,25 @@ class Geometry:
                            fixed_iters, history, check_every, stream)
 
 
+def _per(v, n):
+    return list(v) if isinstance(v, (list, tuple)) else [v] * n
+
+
 def solve_batch(geoms, bs, xs, tol=1e-3, max_iter=1000, lam=0.0, precond=PRECOND_WMG,
-                fixed_iters=0, stream=None):
-    """Solve many CGLS problems together; returns a list of info dicts."""
+                fixed_iters=0, check_every=0, stream=None):
+    """Solve many CGLS problems together; returns a list of info dicts.
+
+    tol, max_iter, lam, precond and fixed_iters are scalars or per-problem lists."""
     n = len(geoms)
+    if not (len(bs) == n and len(xs) == n):
+        raise ValueError("geoms, bs and xs must have the same length")
     GA = (C.c_void_p * n)(*[g.handle.value for g in geoms])
     BA = (C.c_void_p * n)(*[g._sino(b, "b").value for g, b in zip(geoms, bs)])
     XA = (C.c_void_p * n)(*[g._img(x, "x").value for g, x in zip(geoms, xs)])
-    tols = tol if isinstance(tol, (list, tuple)) else [tol] * n
-    OA = (SolveOpts * n)(*[SolveOpts(float(t), int(max_iter), 30, float(lam), int(precond), 0,
-                                     None, 0, int(fixed_iters)) for t in tols])
+    opts = zip(_per(tol, n), _per(max_iter, n), _per(lam, n), _per(precond, n),
+               _per(fixed_iters, n))
+    OA = (SolveOpts * n)(*[SolveOpts(float(t), int(mi), 30, float(la), int(pc), int(check_every),
+                                     None, 0, int(fi)) for t, mi, la, pc, fi in opts])
     IA = (SolveInfo * n)()
     rc = _lib.reco_solve_batch(n, GA, BA, XA, OA, IA, _stream(stream))
     _check(rc, allow=(RECO_OK, RECO_ENOTCONV, RECO_ENUMERIC))
@@ -293,6 +303,16 @@ class Server:
 
     def submit(self, n, n_angles, n_bins, wmg_levels, b, x, tol=1e-3, max_iter=1000,
                precond=PRECOND_WMG, lam=0.0, fixed_iters=0):
+        """Queue a request; b and x are float32 device tensors that must stay alive
+        (and b unchanged) until poll() returns a result.  The current stream is
+        synchronised first so that b is complete when the server reads it."""
+        import torch
+        for t, size, name in ((b, n_angles * n_bins, "b"), (x, n * n, "x")):
+            if (not t.is_cuda or t.dtype != torch.float32 or not t.is_contiguous()
+                    or t.numel() != size):
+                raise ValueError(f"{name} must be a contiguous float32 GPU tensor of {size} "
+                                 "elements")
+        torch.cuda.current_stream().synchronize()
         desc = GeometryDesc(n, n_angles, n_bins, wmg_levels, F32, 0)
         opts = SolveOpts(float(tol), int(max_iter), 30, float(lam), int(precond), 0, None, 0,
                          int(fixed_iters))
@@ -307,7 +327,7 @@ class Server:
         rc = _lib.reco_poll(self.handle, C.c_uint64(ticket), C.byref(info), ts)
         if rc == RECO_PENDING:
             return None
-        _check(rc, allow=(RECO_OK, RECO_ENOTCONV, RECO_ENUMERIC, RECO_ENOMEM))
+        _check(rc, allow=(RECO_OK, RECO_ENOTCONV, RECO_ENUMERIC))
         d = info.as_dict()
         d["status_code"] = rc
         d["t_submit"], d["t_admit"], d["t_done"] = ts[0], ts[1], ts[2]

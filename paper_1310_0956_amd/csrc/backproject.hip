@@ -87,7 +87,7 @@ template <typename T>
 constexpr int kGroups = sizeof(T) == 4 ? 4 : 2;
 
 template <typename T, int MODE>
-__global__ __launch_bounds__(kThreads * kGroups<T>) void k_backward(BwdK<T> a) {
+__device__ __forceinline__ void backward_body(const BwdK<T>& a, const BlockPos pos) {
   constexpr int G = kGroups<T>;
   if (a.st && a.st->done) return;   // solver finished: later launches are no-ops
   __shared__ T win[G][2][kChunk * kWin];
@@ -96,12 +96,12 @@ __global__ __launch_bounds__(kThreads * kGroups<T>) void k_backward(BwdK<T> a) {
   const int grp = __builtin_amdgcn_readfirstlane((int)threadIdx.x / kThreads);
   const int t = threadIdx.x - grp * kThreads;
   const int tx = t & (kTile - 1), ty = t / kTile;          // ty in [0, 8)
-  const int ix = blockIdx.x * kTile + tx;
-  const int iy0 = blockIdx.y * kTile + ty, iy1 = iy0 + 8;
+  const int ix = pos.x * kTile + tx;
+  const int iy0 = pos.y * kTile + ty, iy1 = iy0 + 8;
   const int n = a.n, nb = a.nb, m = a.m;
   const double hc = 0.5 * (n - 1), hb = 0.5 * (nb - 1);
-  const double Xc = blockIdx.x * kTile + 0.5 * (kTile - 1) - hc;
-  const double Yc = blockIdx.y * kTile + 0.5 * (kTile - 1) - hc;
+  const double Xc = pos.x * kTile + 0.5 * (kTile - 1) - hc;
+  const double Yc = pos.y * kTile + 0.5 * (kTile - 1) - hc;
   const T dX = T(tx) - T(0.5 * (kTile - 1)), dY = T(ty) - T(0.5 * (kTile - 1));
   T acc0 = T(0), acc1 = T(0);
   const int nchunks = (m + kChunk - 1) / kChunk;
@@ -193,7 +193,7 @@ __global__ __launch_bounds__(kThreads * kGroups<T>) void k_backward(BwdK<T> a) {
     double v[1] = {usq};
     SolverState* sst = a.st;
     reduce_and_finish<1, kThreads * G / 64>(
-        v, a.red, gridDim.x * gridDim.y, blockIdx.y * gridDim.x + blockIdx.x,
+        v, a.red, pos.count(), pos.id(),
         [sst](double (&tot)[1]) {
           const double nrm = sqrt(tot[0]);
           if (!sst->init) {
@@ -236,8 +236,21 @@ __global__ __launch_bounds__(kThreads * kGroups<T>) void k_backward(BwdK<T> a) {
   }
 }
 
+template <typename T, int MODE>
+__global__ __launch_bounds__(kThreads * kGroups<T>) void k_backward(BwdK<T> a) {
+  backward_body<T, MODE>(a, grid_pos());
+}
+
+template <typename T, int MODE>
+__global__ __launch_bounds__(kThreads * kGroups<T>) void k_backward_batch(
+    const BwdK<T>* __restrict__ args, const int* __restrict__ start, const int* __restrict__ gx,
+    int count) {
+  const int r = batch_find(start, count, blockIdx.x);
+  backward_body<T, MODE>(args[r], batch_pos(start, gx, r));
+}
+
 template <typename T>
-void bwd_dispatch(const Geometry& g, BwdMode mode, const BwdArgs& a, hipStream_t st) {
+BwdK<T> bwd_args(const Geometry& g, const BwdArgs& a) {
   BwdK<T> k;
   k.sino = (const T*)a.sino;
   k.out = (T*)a.out;
@@ -256,6 +269,12 @@ void bwd_dispatch(const Geometry& g, BwdMode mode, const BwdArgs& a, hipStream_t
   k.sa = a.sa;
   k.sx = a.sx;
   k.sf = a.sf;
+  return k;
+}
+
+template <typename T>
+void bwd_dispatch(const Geometry& g, BwdMode mode, const BwdArgs& a, hipStream_t st) {
+  const BwdK<T> k = bwd_args<T>(g, a);
   dim3 grid((g.n + kTile - 1) / kTile, (g.n + kTile - 1) / kTile);
   const dim3 block(kThreads * kGroups<T>);
   TimedLaunch tl(TK_BACKWARD, st);
@@ -278,6 +297,38 @@ int backward_blocks(const Geometry& g) {
 void launch_backward(const Geometry& g, BwdMode mode, const BwdArgs& a, hipStream_t st) {
   if (g.f64) bwd_dispatch<double>(g, mode, a, st);
   else bwd_dispatch<float>(g, mode, a, st);
+}
+
+void prepare_backward_batch(DevTable& t, const std::vector<const Geometry*>& gs,
+                            const std::vector<BwdArgs>& as, hipStream_t st) {
+  std::vector<BwdK<float>> host(gs.size());
+  std::vector<int> blocks(gs.size()), widths(gs.size());
+  for (size_t i = 0; i < gs.size(); ++i) {
+    if (gs[i]->f64) fail(RECO_EINVAL, "batched solves take float32 geometries");
+    host[i] = bwd_args<float>(*gs[i], as[i]);
+    widths[i] = (gs[i]->n + kTile - 1) / kTile;
+    blocks[i] = widths[i] * widths[i];
+  }
+  t.upload(host.data(), sizeof(BwdK<float>), blocks, widths, st);
+}
+
+void launch_backward_batch(const DevTable& t, BwdMode mode, hipStream_t st) {
+  if (t.count == 0) return;
+  TimedLaunch tl(TK_BACKWARD, st);
+  const auto* args = (const BwdK<float>*)t.args;
+  const dim3 block(kThreads * kGroups<float>);
+  switch (mode) {
+    case BWD_CGLS:
+      hipLaunchKernelGGL((k_backward_batch<float, BWD_CGLS>), dim3(t.total_blocks), block, 0, st,
+                         args, t.start, t.gx, t.count);
+      break;
+    case BWD_PLAIN:
+      hipLaunchKernelGGL((k_backward_batch<float, BWD_PLAIN>), dim3(t.total_blocks), block, 0, st,
+                         args, t.start, t.gx, t.count);
+      break;
+    default: fail(RECO_EINVAL, "unsupported batched backward mode");
+  }
+  HIP_CHECK(hipGetLastError());
 }
 
 }  // namespace reco

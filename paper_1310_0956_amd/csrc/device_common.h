@@ -97,4 +97,33 @@ __device__ __forceinline__ void reduce_and_finish(double (&v)[W], const RedScrat
 
 __device__ __forceinline__ bool finite(double v) { return __builtin_isfinite(v); }
 
+// Position of a block within its problem's grid.
+struct BlockPos {
+  int x, y, gx, gy;
+  __device__ __forceinline__ int id() const { return y * gx + x; }
+  __device__ __forceinline__ int count() const { return gx * gy; }
+};
+
+__device__ __forceinline__ BlockPos grid_pos() {
+  return BlockPos{(int)blockIdx.x, (int)blockIdx.y, (int)gridDim.x, (int)gridDim.y};
+}
+
+// Problem owning flat block b in a batched launch: the last r with start[r] <= b.
+__device__ __forceinline__ int batch_find(const int* __restrict__ start, int count, int b) {
+  int lo = 0, hi = count - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (start[mid] <= b) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+__device__ __forceinline__ BlockPos batch_pos(const int* __restrict__ start,
+                                              const int* __restrict__ gx, int r) {
+  const int lb = (int)blockIdx.x - start[r];
+  const int w = gx[r];
+  return BlockPos{lb % w, lb / w, w, (start[r + 1] - start[r]) / w};
+}
+
 }  // namespace reco

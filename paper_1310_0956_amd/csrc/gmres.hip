@@ -406,6 +406,7 @@ reco_status solve_gmres(Geometry& g, const void* b, void* x, const reco_solve_op
   Workspace* w = checkout_workspace(g, st);
   reco_status rc;
   try {
+    ensure_aux(g, *w);
     rc = g.f64 ? gmres_impl<double>(g, b, x, o, info, st, *w)
                : gmres_impl<float>(g, b, x, o, info, st, *w);
   } catch (...) {

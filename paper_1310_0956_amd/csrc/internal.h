@@ -145,6 +145,23 @@ struct RedScratch {
 };
 
 // ---------------------------------------------------------------------------
+// Batched launches: one launch covers the blocks of many problems.  A device
+// table holds each problem's kernel arguments, the prefix sums of their block
+// counts and their grid widths; a block finds its problem by binary search.
+// ---------------------------------------------------------------------------
+struct DevTable {
+  void* args = nullptr;     // [count] kernel argument structs
+  int* start = nullptr;     // [count + 1] first flat block of each problem
+  int* gx = nullptr;        // [count] grid width of each problem
+  int count = 0;
+  int total_blocks = 0;
+  size_t args_cap = 0, idx_cap = 0;
+  void upload(const void* host_args, size_t arg_size, const std::vector<int>& blocks,
+              const std::vector<int>& widths, hipStream_t st);
+  ~DevTable();
+};
+
+// ---------------------------------------------------------------------------
 // Kernel launchers (project.hip, backproject.hip, wmg.hip, vec.hip)
 // ---------------------------------------------------------------------------
 enum FwdMode { FWD_PLAIN = 0, FWD_CGLS = 1, FWD_SIRT = 2, FWD_COUNT = 3 };
@@ -205,5 +222,36 @@ void launch_cgls_update(const Geometry& g, void* x, void* p, const void* zP, voi
 void launch_invert(void* v, size_t count, bool f64, hipStream_t st);
 void launch_state_init(SolverState* st, double tol, int max_iter, int fixed, double lambda,
                        double* hist, int hist_cap, hipStream_t s);
+
+// batched forms (float problems); the tables are filled by prepare_* and the
+// launches may be captured in a HIP graph and replayed.
+void prepare_forward_batch(DevTable& t, const std::vector<const Geometry*>& gs,
+                           const std::vector<FwdArgs>& as, hipStream_t st);
+void launch_forward_batch(const DevTable& t, FwdMode mode, hipStream_t st);
+void prepare_backward_batch(DevTable& t, const std::vector<const Geometry*>& gs,
+                            const std::vector<BwdArgs>& as, hipStream_t st);
+void launch_backward_batch(const DevTable& t, BwdMode mode, hipStream_t st);
+void prepare_wmg_batch(DevTable& t, const std::vector<const Geometry*>& gs,
+                       const std::vector<WmgArgs>& as, hipStream_t st);
+void launch_wmg_batch(const DevTable& t, WmgMode mode, hipStream_t st);
+struct UpdArgs {
+  void *x, *p, *r;
+  const void *zP, *q;
+  SolverState* st;
+};
+void prepare_update_batch(DevTable& t, const std::vector<const Geometry*>& gs,
+                          const std::vector<UpdArgs>& as, hipStream_t st);
+void launch_update_batch(const DevTable& t, hipStream_t st);
+struct InitArgs {
+  void *x, *p, *q, *r;
+  const void* b;
+  SolverState* st;
+  double tol, lambda;
+  double* hist;
+  int max_iter, fixed, hist_cap;
+};
+void prepare_init_batch(DevTable& t, const std::vector<const Geometry*>& gs,
+                        const std::vector<InitArgs>& as, hipStream_t st);
+void launch_init_batch(const DevTable& t, hipStream_t st);
 
 }  // namespace reco

@@ -213,7 +213,7 @@ __device__ __forceinline__ Window band_window(const FwdAngle& ca, bool cvalid, i
 }
 
 template <typename T, int MODE>
-__global__ __launch_bounds__(kThreads) void k_forward(FwdK<T> a) {
+__device__ __forceinline__ void forward_body(const FwdK<T>& a, const BlockPos bp) {
   constexpr int BAND = kBand<T>;
   constexpr int STAGE_PER = BAND / kStageRows;   // loads per thread per band
   if (a.st && a.st->done) return;   // solver finished: later launches are no-ops
@@ -222,8 +222,8 @@ __global__ __launch_bounds__(kThreads) void k_forward(FwdK<T> a) {
   const int t = threadIdx.x;
   const int lane = t & 63, wv = t >> 6;
   const int n = a.n, nb = a.nb;
-  const int g = blockIdx.y;
-  const int jfirst = blockIdx.x * kBins;
+  const int g = bp.y;
+  const int jfirst = bp.x * kBins;
   const int jlast = min(jfirst + kBins - 1, nb - 1);
   const int k0 = a.groups[g * kSlots];            // first angle: sets the walk axis
   const int kl = a.groups[g * kSlots + (t >> 5)];
@@ -352,8 +352,7 @@ __global__ __launch_bounds__(kThreads) void k_forward(FwdK<T> a) {
     }
     double v[1] = {q * q};
     SolverState* st = a.st;
-    const int nblk = gridDim.x * gridDim.y;
-    reduce_and_finish<1, kThreads / 64>(v, a.red, nblk, blockIdx.y * gridDim.x + blockIdx.x,
+    reduce_and_finish<1, kThreads / 64>(v, a.red, bp.count(), bp.id(),
                                         [st](double (&tot)[1]) {
                                           const double delta = tot[0] + st->lambda * st->pp;
                                           st->delta = delta;
@@ -368,6 +367,19 @@ __global__ __launch_bounds__(kThreads) void k_forward(FwdK<T> a) {
                                           }
                                         });
   }
+}
+
+template <typename T, int MODE>
+__global__ __launch_bounds__(kThreads) void k_forward(FwdK<T> a) {
+  forward_body<T, MODE>(a, grid_pos());
+}
+
+template <typename T, int MODE>
+__global__ __launch_bounds__(kThreads) void k_forward_batch(const FwdK<T>* __restrict__ args,
+                                                            const int* __restrict__ start,
+                                                            const int* __restrict__ gx, int count) {
+  const int r = batch_find(start, count, blockIdx.x);
+  forward_body<T, MODE>(args[r], batch_pos(start, gx, r));
 }
 
 // Nonzero count of W: one thread per ray, every row of the image, float64
@@ -485,6 +497,37 @@ int forward_blocks(const Geometry& g) { return ((g.nb + kBins - 1) / kBins) * g.
 void launch_forward(const Geometry& g, FwdMode mode, const FwdArgs& a, hipStream_t st) {
   if (g.f64) fwd_dispatch<double>(g, mode, a, st);
   else fwd_dispatch<float>(g, mode, a, st);
+}
+
+void prepare_forward_batch(DevTable& t, const std::vector<const Geometry*>& gs,
+                           const std::vector<FwdArgs>& as, hipStream_t st) {
+  std::vector<FwdK<float>> host(gs.size());
+  std::vector<int> blocks(gs.size()), widths(gs.size());
+  for (size_t i = 0; i < gs.size(); ++i) {
+    if (gs[i]->f64) fail(RECO_EINVAL, "batched solves take float32 geometries");
+    host[i] = make_args<float>(*gs[i], as[i]);
+    widths[i] = (gs[i]->nb + kBins - 1) / kBins;
+    blocks[i] = widths[i] * gs[i]->ngroups;
+  }
+  t.upload(host.data(), sizeof(FwdK<float>), blocks, widths, st);
+}
+
+void launch_forward_batch(const DevTable& t, FwdMode mode, hipStream_t st) {
+  if (t.count == 0) return;
+  TimedLaunch tl(TK_FORWARD, st);
+  const auto* args = (const FwdK<float>*)t.args;
+  switch (mode) {
+    case FWD_PLAIN:
+      hipLaunchKernelGGL((k_forward_batch<float, FWD_PLAIN>), dim3(t.total_blocks), dim3(kThreads), 0,
+                         st, args, t.start, t.gx, t.count);
+      break;
+    case FWD_CGLS:
+      hipLaunchKernelGGL((k_forward_batch<float, FWD_CGLS>), dim3(t.total_blocks), dim3(kThreads), 0,
+                         st, args, t.start, t.gx, t.count);
+      break;
+    default: fail(RECO_EINVAL, "unsupported batched forward mode");
+  }
+  HIP_CHECK(hipGetLastError());
 }
 
 void launch_pad_transpose(const Geometry& g, const void* x, void* xP, void* xTP, hipStream_t st) {

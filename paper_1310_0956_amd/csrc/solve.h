@@ -10,6 +10,7 @@ struct Workspace {
   void *r = nullptr, *q = nullptr;            // [M] residual, projected direction
   void *s = nullptr, *p = nullptr;            // [N] normal-equation residual, direction
   void *zP = nullptr, *zTP = nullptr;         // padded preconditioned residual (+ transpose)
+  // allocated on first use by SIRT / GMRES (CGLS needs none of them):
   void *xP = nullptr, *xTP = nullptr;         // padded iterate copies (SIRT, GMRES)
   void *tmp = nullptr;                        // [max(N, M)]
   void *fvec = nullptr;                       // [N] right-hand side W^T b (GMRES)
@@ -29,7 +30,17 @@ struct Workspace {
 Workspace* checkout_workspace(Geometry& g, hipStream_t st);
 void return_workspace(Geometry& g, Workspace* w);
 void release_workspaces(Geometry& g);
+void ensure_aux(Geometry& g, Workspace& w);     // xP, xTP, tmp, fvec
+void ensure_history(Workspace& w, int cap);
 RedScratch red_of(Workspace& w, int slot);
+// Device bytes of one CGLS workspace / of a geometry's own tables, for the
+// geometry described by d (used for admission by memory budget).
+size_t cgls_workspace_bytes(const reco_geometry_desc& d);
+size_t geometry_bytes(const reco_geometry_desc& d);
+
+void validate_opts(const reco_solve_opts& o, bool gmres);
+reco_status status_of(int done);
+double now_ms();
 
 reco_status solve_cgls(Geometry& g, const void* b, void* x, const reco_solve_opts& o,
                        reco_solve_info* info, hipStream_t st);

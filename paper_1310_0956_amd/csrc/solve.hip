@@ -47,10 +47,6 @@ Workspace* checkout_workspace(Geometry& g, hipStream_t st) {
   alloc(&w->p, es * g.N());
   alloc(&w->zP, es * g.padded_elems());
   alloc(&w->zTP, es * g.padded_elems());
-  alloc(&w->xP, es * g.padded_elems());
-  alloc(&w->xTP, es * g.padded_elems());
-  alloc(&w->tmp, es * std::max(g.N(), g.M()));
-  alloc(&w->fvec, es * g.N());
   int cap = std::max(forward_blocks(g), std::max(backward_blocks(g), wmg_blocks(g)));
   w->red_cap = cap * 4;
   alloc((void**)&w->partial, sizeof(double) * w->red_cap);
@@ -63,6 +59,32 @@ Workspace* checkout_workspace(Geometry& g, hipStream_t st) {
   launch_fill(w->zP, g.padded_elems(), g.f64, 0.0, st);
   launch_fill(w->zTP, g.padded_elems(), g.f64, 0.0, st);
   return w.release();
+}
+
+void ensure_aux(Geometry& g, Workspace& w) {
+  const size_t es = g.esize();
+  if (!w.xP) alloc(&w.xP, es * g.padded_elems());
+  if (!w.xTP) alloc(&w.xTP, es * g.padded_elems());
+  if (!w.tmp) alloc(&w.tmp, es * std::max(g.N(), g.M()));
+  if (!w.fvec) alloc(&w.fvec, es * g.N());
+}
+
+size_t cgls_workspace_bytes(const reco_geometry_desc& d) {
+  const size_t es = d.dtype == RECO_F64 ? 8 : 4;
+  const size_t n = (size_t)d.n, N = n * n, M = (size_t)d.n_angles * d.n_bins;
+  const size_t padded = n * (n + 2 * kPad);
+  const size_t tiles = (n + 31) / 32;
+  const size_t fblocks = (size_t)((d.n_bins + 31) / 32) * (size_t)((d.n_angles + 7) / 8 + 2);
+  const size_t blocks = std::max(fblocks, tiles * tiles) * 2;
+  const size_t hist = 8 * 4096;
+  return es * (2 * M + 2 * N + 2 * padded) + sizeof(double) * 4 * blocks + hist + 4096;
+}
+
+size_t geometry_bytes(const reco_geometry_desc& d) {
+  const size_t es = d.dtype == RECO_F64 ? 8 : 4;
+  const size_t N = (size_t)d.n * d.n;
+  return (sizeof(FwdAngle) + sizeof(BwdAngle) + 8 * sizeof(int)) * (size_t)(d.n_angles + 8) +
+         N * (8 + es) + 4096;
 }
 
 void return_workspace(Geometry& g, Workspace* w) {
@@ -100,7 +122,7 @@ struct Lease {
   ~Lease() { return_workspace(g, w); }
 };
 
-static void validate_opts(const reco_solve_opts& o, bool gmres) {
+void validate_opts(const reco_solve_opts& o, bool gmres) {
   if (!(o.tol > 0.0) && o.fixed_iters <= 0) fail(RECO_EINVAL, "tol must be > 0");
   if (o.max_iter < 1 && o.fixed_iters <= 0) fail(RECO_EINVAL, "max_iter must be >= 1");
   if (!(o.lambda >= 0.0)) fail(RECO_EINVAL, "lambda must be >= 0");
@@ -111,7 +133,7 @@ static void validate_opts(const reco_solve_opts& o, bool gmres) {
   if (o.check_every < 0) fail(RECO_EINVAL, "check_every must be >= 0");
 }
 
-static reco_status status_of(int done) {
+reco_status status_of(int done) {
   switch (done) {
     case 1: return RECO_OK;
     case 2: return RECO_ENOTCONV;
@@ -143,7 +165,7 @@ static void finish_info(Workspace& w, const reco_solve_opts& o, reco_solve_info*
   }
 }
 
-static double now_ms() {
+double now_ms() {
   return std::chrono::duration<double, std::milli>(
              std::chrono::steady_clock::now().time_since_epoch()).count();
 }
@@ -281,6 +303,7 @@ reco_status solve_sirt(Geometry& g, const void* b, void* x, const reco_solve_opt
   ensure_sirt_weights(g, st);
   Lease lease(g, st);
   Workspace& w = *lease.w;
+  ensure_aux(g, w);
   const bool fixed = o.fixed_iters > 0;
   const int limit = fixed ? o.fixed_iters : o.max_iter;
   ensure_history(w, limit);

@@ -13,12 +13,14 @@ enum TimedKind {
   TK_UPDATE = 3,       // fused CGLS vector update
   TK_PACKET_DIAG = 4,  // packet-diagonal setup
   TK_PREP = 5,         // image padding / transposition
-  kTimedKinds = 6
+  TK_GRAPH = 6,        // one replay of a batched-iteration graph
+  kTimedKinds = 7
 };
 
 bool timing_on();
 
 // Records an event on `st` when constructed and another when destroyed.
+// Launches made while `st` is being captured into a graph are not timed.
 class TimedLaunch {
  public:
   TimedLaunch(int kind, hipStream_t st);

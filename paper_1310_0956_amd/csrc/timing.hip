@@ -42,6 +42,12 @@ bool timing_on() { return timer().on.load(std::memory_order_relaxed); }
 
 TimedLaunch::TimedLaunch(int kind, hipStream_t st) : kind_(kind), st_(st) {
   if (!timing_on()) return;
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(st, &cs) != hipSuccess) {
+    (void)hipGetLastError();
+    return;
+  }
+  if (cs != hipStreamCaptureStatusNone) return;
   Timer& t = timer();
   std::lock_guard<std::mutex> lk(t.mu);
   a_ = take_event(t);

@@ -34,15 +34,32 @@ __global__ void k_invert(T* p, size_t count) {
 // p = z + beta p; x += alpha p   (pixels, blocks [0, nbN))
 // r -= alpha q                   (rays,   blocks [nbN, ...))
 template <typename T>
-__global__ __launch_bounds__(256) void k_cgls_update(T* __restrict__ x, T* __restrict__ p,
-                                                     const T* __restrict__ zP, T* __restrict__ r,
-                                                     const T* __restrict__ q, const SolverState* st,
-                                                     int n, int ld, size_t M, int nbN) {
+struct UpdK {
+  T* x;
+  T* p;
+  const T* zP;
+  T* r;
+  const T* q;
+  const SolverState* st;
+  int n, ld, nbN;
+  size_t M;
+};
+
+template <typename T>
+__device__ __forceinline__ void update_body(const UpdK<T>& a, int b) {
+  const SolverState* st = a.st;
   if (st->done) return;
   const double alpha = st->alpha, beta = st->beta;
-  if ((int)blockIdx.x < nbN) {
+  T* __restrict__ x = a.x;
+  T* __restrict__ p = a.p;
+  T* __restrict__ r = a.r;
+  const T* __restrict__ zP = a.zP;
+  const T* __restrict__ q = a.q;
+  const int n = a.n, ld = a.ld, nbN = a.nbN;
+  const size_t M = a.M;
+  if (b < nbN) {
     const size_t N = (size_t)n * n;
-    const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+    const size_t i = (size_t)b * 256 + threadIdx.x;
     if (i < N) {
       const size_t iy = i / n, ix = i % n;
       const double z = (double)zP[iy * ld + ix + kPad];
@@ -51,8 +68,59 @@ __global__ __launch_bounds__(256) void k_cgls_update(T* __restrict__ x, T* __res
       x[i] = (T)((double)x[i] + alpha * (double)pn);
     }
   } else {
-    const size_t i = (size_t)(blockIdx.x - nbN) * 256 + threadIdx.x;
+    const size_t i = (size_t)(b - nbN) * 256 + threadIdx.x;
     if (i < M) r[i] = (T)((double)r[i] - alpha * (double)q[i]);
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_cgls_update(UpdK<T> a) {
+  update_body<T>(a, blockIdx.x);
+}
+
+__global__ __launch_bounds__(256) void k_update_batch(const UpdK<float>* __restrict__ args,
+                                                      const int* __restrict__ start,
+                                                      const int* __restrict__ gx, int count) {
+  const int r = batch_find(start, count, blockIdx.x);
+  update_body<float>(args[r], (int)blockIdx.x - start[r]);
+}
+
+// Start of a CGLS solve for one problem of a batch: state, x = p = q = 0, r = b.
+struct InitK {
+  float *x, *p, *q, *r;
+  const float* b;
+  SolverState* st;
+  double tol, lambda;
+  double* hist;
+  int max_iter, fixed, hist_cap;
+  size_t N, M;
+};
+
+__global__ __launch_bounds__(256) void k_init_batch(const InitK* __restrict__ args,
+                                                    const int* __restrict__ start,
+                                                    const int* __restrict__ gx, int count) {
+  const int rr = batch_find(start, count, blockIdx.x);
+  const InitK& a = args[rr];
+  const int lb = (int)blockIdx.x - start[rr];
+  const int nblk = start[rr + 1] - start[rr];
+  if (lb == 0 && threadIdx.x == 0) {
+    SolverState s{};
+    s.tol = a.tol;
+    s.max_iter = a.max_iter;
+    s.fixed = a.fixed;
+    s.lambda = a.lambda;
+    s.hist = a.hist;
+    s.hist_cap = a.hist_cap;
+    *a.st = s;
+  }
+  const size_t stride = (size_t)nblk * 256;
+  for (size_t i = (size_t)lb * 256 + threadIdx.x; i < a.N; i += stride) {
+    a.x[i] = 0.0f;
+    a.p[i] = 0.0f;
+  }
+  for (size_t i = (size_t)lb * 256 + threadIdx.x; i < a.M; i += stride) {
+    a.q[i] = 0.0f;
+    a.r[i] = a.b[i];
   }
 }
 
@@ -71,6 +139,27 @@ __global__ void k_state_init(SolverState* st, double tol, int max_iter, int fixe
 unsigned grid_for(size_t count) {
   size_t b = (count + 255) / 256;
   return (unsigned)(b > 65536 ? 65536 : (b == 0 ? 1 : b));
+}
+
+template <typename T>
+UpdK<T> upd_args(const Geometry& g, void* x, void* p, const void* zP, void* r, const void* q,
+                 const SolverState* st) {
+  UpdK<T> k;
+  k.x = (T*)x;
+  k.p = (T*)p;
+  k.zP = (const T*)zP;
+  k.r = (T*)r;
+  k.q = (const T*)q;
+  k.st = st;
+  k.n = g.n;
+  k.ld = g.ld;
+  k.nbN = (int)((g.N() + 255) / 256);
+  k.M = g.M();
+  return k;
+}
+
+int update_blocks(const Geometry& g) {
+  return (int)((g.N() + 255) / 256) + (int)((g.M() + 255) / 256);
 }
 
 }  // namespace
@@ -98,17 +187,68 @@ void launch_invert(void* v, size_t count, bool f64, hipStream_t st) {
 
 void launch_cgls_update(const Geometry& g, void* x, void* p, const void* zP, void* r, const void* q,
                         SolverState* st, hipStream_t s) {
-  const int nbN = (int)((g.N() + 255) / 256);
-  const int nbM = (int)((g.M() + 255) / 256);
   TimedLaunch tl(TK_UPDATE, s);
   if (g.f64)
-    hipLaunchKernelGGL(k_cgls_update<double>, dim3(nbN + nbM), dim3(256), 0, s, (double*)x,
-                       (double*)p, (const double*)zP, (double*)r, (const double*)q, st, g.n, g.ld,
-                       g.M(), nbN);
+    hipLaunchKernelGGL(k_cgls_update<double>, dim3(update_blocks(g)), dim3(256), 0, s,
+                       upd_args<double>(g, x, p, zP, r, q, st));
   else
-    hipLaunchKernelGGL(k_cgls_update<float>, dim3(nbN + nbM), dim3(256), 0, s, (float*)x,
-                       (float*)p, (const float*)zP, (float*)r, (const float*)q, st, g.n, g.ld,
-                       g.M(), nbN);
+    hipLaunchKernelGGL(k_cgls_update<float>, dim3(update_blocks(g)), dim3(256), 0, s,
+                       upd_args<float>(g, x, p, zP, r, q, st));
+  HIP_CHECK(hipGetLastError());
+}
+
+void prepare_update_batch(DevTable& t, const std::vector<const Geometry*>& gs,
+                          const std::vector<UpdArgs>& as, hipStream_t st) {
+  std::vector<UpdK<float>> host(gs.size());
+  std::vector<int> blocks(gs.size()), widths(gs.size());
+  for (size_t i = 0; i < gs.size(); ++i) {
+    host[i] = upd_args<float>(*gs[i], as[i].x, as[i].p, as[i].zP, as[i].r, as[i].q, as[i].st);
+    blocks[i] = update_blocks(*gs[i]);
+    widths[i] = blocks[i];
+  }
+  t.upload(host.data(), sizeof(UpdK<float>), blocks, widths, st);
+}
+
+void launch_update_batch(const DevTable& t, hipStream_t st) {
+  if (t.count == 0) return;
+  TimedLaunch tl(TK_UPDATE, st);
+  hipLaunchKernelGGL(k_update_batch, dim3(t.total_blocks), dim3(256), 0, st,
+                     (const UpdK<float>*)t.args, t.start, t.gx, t.count);
+  HIP_CHECK(hipGetLastError());
+}
+
+void prepare_init_batch(DevTable& t, const std::vector<const Geometry*>& gs,
+                        const std::vector<InitArgs>& as, hipStream_t st) {
+  std::vector<InitK> host(gs.size());
+  std::vector<int> blocks(gs.size()), widths(gs.size());
+  for (size_t i = 0; i < gs.size(); ++i) {
+    InitK k;
+    k.x = (float*)as[i].x;
+    k.p = (float*)as[i].p;
+    k.q = (float*)as[i].q;
+    k.r = (float*)as[i].r;
+    k.b = (const float*)as[i].b;
+    k.st = as[i].st;
+    k.tol = as[i].tol;
+    k.lambda = as[i].lambda;
+    k.hist = as[i].hist;
+    k.max_iter = as[i].max_iter;
+    k.fixed = as[i].fixed;
+    k.hist_cap = as[i].hist_cap;
+    k.N = gs[i]->N();
+    k.M = gs[i]->M();
+    host[i] = k;
+    const size_t big = std::max(k.N, k.M);
+    blocks[i] = (int)std::min<size_t>((big + 1023) / 1024, 4096);
+    widths[i] = blocks[i];
+  }
+  t.upload(host.data(), sizeof(InitK), blocks, widths, st);
+}
+
+void launch_init_batch(const DevTable& t, hipStream_t st) {
+  if (t.count == 0) return;
+  hipLaunchKernelGGL(k_init_batch, dim3(t.total_blocks), dim3(256), 0, st,
+                     (const InitK*)t.args, t.start, t.gx, t.count);
   HIP_CHECK(hipGetLastError());
 }
 

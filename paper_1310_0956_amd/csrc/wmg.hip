@@ -35,6 +35,8 @@ struct WmgK {
   SolverState* st;
   RedScratch red;
   int n, ld;
+  int L;           // packet levels (batched launches dispatch on it)
+  int identity;    // 1: no preconditioner (batched launches dispatch on it)
   double lambda;
 };
 
@@ -72,11 +74,11 @@ __device__ __forceinline__ void wht_region(T (&tile)[32][33]) {
 }
 
 template <typename T, int L, int MODE, bool IDENT>
-__global__ __launch_bounds__(256) void k_wmg(WmgK<T> a) {
+__device__ __forceinline__ void wmg_body(const WmgK<T>& a, const BlockPos bp) {
   if (a.st && a.st->done) return;   // solver finished: later launches are no-ops
   __shared__ T tile[32][33];
   const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
-  const int x0 = blockIdx.x * 32, y0 = blockIdx.y * 32;
+  const int x0 = bp.x * 32, y0 = bp.y * 32;
   const int n = a.n;
   T sv[4];
 #pragma unroll
@@ -133,7 +135,7 @@ __global__ __launch_bounds__(256) void k_wmg(WmgK<T> a) {
         v[3] += z * (double)a.pold[(size_t)iy * n + ix];
     }
     SolverState* st = a.st;
-    reduce_and_finish<4>(v, a.red, gridDim.x * gridDim.y, blockIdx.y * gridDim.x + blockIdx.x,
+    reduce_and_finish<4>(v, a.red, bp.count(), bp.id(),
                          [st](double (&t)[4]) {
                            if (MODE == WMG_CGLS_INIT) {
                              st->gamma = t[0];
@@ -165,8 +167,35 @@ __global__ __launch_bounds__(256) void k_wmg(WmgK<T> a) {
   }
 }
 
-template <typename T, int L>
-void wmg_launch_L(const Geometry& g, WmgMode mode, const WmgArgs& a, hipStream_t st) {
+template <typename T, int L, int MODE, bool IDENT>
+__global__ __launch_bounds__(256) void k_wmg(WmgK<T> a) {
+  wmg_body<T, L, MODE, IDENT>(a, grid_pos());
+}
+
+// Batched apply: the level count and the preconditioner switch are per problem.
+template <int MODE>
+__global__ __launch_bounds__(256) void k_wmg_batch(const WmgK<float>* __restrict__ args,
+                                                   const int* __restrict__ start,
+                                                   const int* __restrict__ gx, int count) {
+  const int r = batch_find(start, count, blockIdx.x);
+  const WmgK<float>& a = args[r];
+  const BlockPos bp = batch_pos(start, gx, r);
+  if (a.identity) {
+    wmg_body<float, 0, MODE, true>(a, bp);
+    return;
+  }
+  switch (a.L) {
+    case 0: wmg_body<float, 0, MODE, false>(a, bp); break;
+    case 1: wmg_body<float, 1, MODE, false>(a, bp); break;
+    case 2: wmg_body<float, 2, MODE, false>(a, bp); break;
+    case 3: wmg_body<float, 3, MODE, false>(a, bp); break;
+    case 4: wmg_body<float, 4, MODE, false>(a, bp); break;
+    default: wmg_body<float, 5, MODE, false>(a, bp); break;
+  }
+}
+
+template <typename T>
+WmgK<T> wmg_args(const Geometry& g, const WmgArgs& a) {
   WmgK<T> k;
   k.s = (const T*)a.s;
   k.z = (T*)a.z;
@@ -178,7 +207,15 @@ void wmg_launch_L(const Geometry& g, WmgMode mode, const WmgArgs& a, hipStream_t
   k.red = a.red;
   k.n = g.n;
   k.ld = g.ld;
+  k.L = g.L;
+  k.identity = a.identity ? 1 : 0;
   k.lambda = a.lambda;
+  return k;
+}
+
+template <typename T, int L>
+void wmg_launch_L(const Geometry& g, WmgMode mode, const WmgArgs& a, hipStream_t st) {
+  const WmgK<T> k = wmg_args<T>(g, a);
   dim3 grid((g.n + 31) / 32, (g.n + 31) / 32);
   TimedLaunch tl(TK_WMG, st);
 #define RECO_WMG_CASE(M)                                                                   \
@@ -343,6 +380,38 @@ int wmg_blocks(const Geometry& g) {
 void launch_wmg(const Geometry& g, WmgMode mode, const WmgArgs& a, hipStream_t st) {
   if (g.f64) wmg_launch<double>(g, mode, a, st);
   else wmg_launch<float>(g, mode, a, st);
+}
+
+void prepare_wmg_batch(DevTable& t, const std::vector<const Geometry*>& gs,
+                       const std::vector<WmgArgs>& as, hipStream_t st) {
+  std::vector<WmgK<float>> host(gs.size());
+  std::vector<int> blocks(gs.size()), widths(gs.size());
+  for (size_t i = 0; i < gs.size(); ++i) {
+    if (gs[i]->f64) fail(RECO_EINVAL, "batched solves take float32 geometries");
+    if (gs[i]->L > 5) fail(RECO_EINVAL, "unsupported number of packet levels");
+    host[i] = wmg_args<float>(*gs[i], as[i]);
+    widths[i] = (gs[i]->n + 31) / 32;
+    blocks[i] = widths[i] * widths[i];
+  }
+  t.upload(host.data(), sizeof(WmgK<float>), blocks, widths, st);
+}
+
+void launch_wmg_batch(const DevTable& t, WmgMode mode, hipStream_t st) {
+  if (t.count == 0) return;
+  TimedLaunch tl(TK_WMG, st);
+  const auto* args = (const WmgK<float>*)t.args;
+  switch (mode) {
+    case WMG_CGLS:
+      hipLaunchKernelGGL(k_wmg_batch<WMG_CGLS>, dim3(t.total_blocks), dim3(256), 0, st, args,
+                         t.start, t.gx, t.count);
+      break;
+    case WMG_CGLS_INIT:
+      hipLaunchKernelGGL(k_wmg_batch<WMG_CGLS_INIT>, dim3(t.total_blocks), dim3(256), 0, st, args,
+                         t.start, t.gx, t.count);
+      break;
+    default: fail(RECO_EINVAL, "unsupported batched WMG mode");
+  }
+  HIP_CHECK(hipGetLastError());
 }
 
 void compute_packet_diagonal(Geometry& g, hipStream_t st) {

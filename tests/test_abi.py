@@ -52,3 +52,10 @@ def test_invalid_arguments_rejected_without_gpu_work():
     assert lib.reco_solve_cgls(None, None, None, None, None, None) == reco.RECO_EINVAL
     assert lib.reco_solve_batch(-1, None, None, None, None, None, None) == reco.RECO_EINVAL
     assert lib.reco_solve_batch(0, None, None, None, None, None, None) == reco.RECO_OK
+    assert lib.reco_solve_batch(1, None, None, None, None, None, None) == reco.RECO_EINVAL
+    assert lib.reco_server_create(0, 4, ctypes.byref(out)) == reco.RECO_EINVAL
+    assert lib.reco_server_create(1 << 20, 0, ctypes.byref(out)) == reco.RECO_EINVAL
+    assert lib.reco_server_create(1 << 20, 4, None) == reco.RECO_EINVAL
+    assert lib.reco_submit(None, None, None, None, None, None) == reco.RECO_EINVAL
+    assert lib.reco_poll(None, 1, None, None) == reco.RECO_EINVAL
+    assert lib.reco_server_destroy(None) == reco.RECO_OK
