@@ -30,6 +30,7 @@ WORKLOAD = dict(n=512, m=360, nb=725, levels=3, ellipses=20, noise=0.01, seed=10
 # exact-length weight (one fused multiply-add and one clamp), accumulate it
 # (one fused multiply-add) and advance the ray or pixel position (one add).
 ALG_OPS_PER_UPDATE = 4.0
+COPY_BYTES = 256 << 20
 
 
 def parse():
@@ -38,8 +39,16 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-iters", type=int, default=3,
-                    help="oracle iterations timed for the CPU baseline sample")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0,
+                    help="approximate CPU time spent on oracle reconstructions")
+    ap.add_argument("--batch", type=int, default=256,
+                    help="reconstructions in the batched leg (0: skip)")
+    ap.add_argument("--serve", type=int, default=120,
+                    help="requests in the serving leg (0: skip)")
+    ap.add_argument("--serve-rate", type=float, default=20.0, help="arrivals per second")
+    ap.add_argument("--serve-budget-gib", type=float, default=64.0)
+    ap.add_argument("--serve-slots", type=int, default=64)
+    ap.add_argument("--no-ct2048", action="store_true", help="skip the 2048^2 leg")
     ap.add_argument("--profile-only", action="store_true",
                     help="only run the timed steps (for rocprofv3)")
     return ap.parse_args()
@@ -63,26 +72,30 @@ def make_inputs(reco, torch, g, count):
     return sinos
 
 
-def source_hash(name):
-    p = os.path.join(ROOT, "paper_1310_0956_amd", "csrc", name)
-    return hashlib.sha256(open(p, "rb").read()).hexdigest()[:16]
+def source_hash(files):
+    m = hashlib.sha256()
+    for name in files:
+        m.update(open(os.path.join(ROOT, "paper_1310_0956_amd", "csrc", name), "rb").read())
+    return m.hexdigest()[:16]
 
 
-def traffic_for(kernel_file, per_launch_default=None):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
-    was taken on the current kernel source (else None)."""
+def traffic_for(family):
+    """Calibrated HBM bytes per launch of a kernel family from the committed
+    rocprofv3 counter summary, if it was taken on the current kernel sources
+    (else None)."""
     p = os.path.join(ROOT, "profiles", "traffic_ct512.json")
     if not os.path.exists(p):
-        return per_launch_default
-    d = json.load(open(p))
-    ent = d.get(kernel_file)
-    if not ent or ent.get("source_sha256_16") != source_hash(kernel_file):
+        return None
+    ent = json.load(open(p)).get(family)
+    if not ent or ent.get("source_sha256_16") != source_hash(ent["source_files"]):
         return None
     return ent.get("bytes_per_launch")
 
 
 def cpu_baseline(args):
-    """Oracle WMG-CGLS on the host, a bounded sample of the same workload."""
+    """Oracle WMG-CGLS on the host: whole reconstructions of the same workload,
+    repeated until about ten seconds of CPU time (matrix assembly and packet
+    diagonal are setup, as on the GPU)."""
     import numpy as np
     import inputs
     from oracle import solvers, wmg
@@ -93,19 +106,211 @@ def cpu_baseline(args):
     W = system_matrix(og)
     L = w["levels"] - 1
     d = wmg.packet_diagonal_by_angles(og, L)
-    x = inputs.ellipse_phantom(w["n"], w["ellipses"], w["seed"])
-    b = W @ x.ravel()
-    b = b + w["noise"] * np.abs(b).max() * inputs.standard_normal(b.size, w["seed"] + 500000)
-    b = b.astype(np.float32).astype(np.float64)
     M = lambda v: wmg.apply_additive_diag(v, d, L)  # noqa: E731
+    solved, iters, t_sum = 0, [], 0.0
+    while solved < 1 or (t_sum < args.cpu_seconds and solved < 8):
+        x = inputs.ellipse_phantom(w["n"], w["ellipses"], w["seed"] + solved)
+        b = W @ x.ravel()
+        e = inputs.standard_normal(b.size, w["seed"] + solved + 500000)
+        b = (b + w["noise"] * np.abs(b).max() * e).astype(np.float32).astype(np.float64)
+        t0 = time.perf_counter()
+        res = solvers.pcgls(W, b, tol=w["tol"], max_iter=1000, precond=M)
+        t_sum += time.perf_counter() - t0
+        iters.append(res.iters)
+        solved += 1
+    return solved, t_sum, iters
+
+
+def percentiles(v):
+    import numpy as np
+    return (round(float(np.percentile(v, 50)), 4), round(float(np.percentile(v, 99)), 4))
+
+
+def gpu_sinogram(torch, g, n_ellipses, seed, noise):
+    """Seeded phantom projected on the device plus seeded Gaussian noise."""
+    import numpy as np
+    import inputs
+    x = torch.from_numpy(inputs.ellipse_phantom(g.n, n_ellipses, seed).astype(np.float32)).cuda()
+    b = g.project(x)
+    torch.cuda.synchronize()
+    e = inputs.standard_normal(g.m * g.nb, seed + 500000)
+    b += torch.from_numpy((noise * float(b.abs().max()) * e).astype(np.float32)).cuda().view_as(b)
+    torch.cuda.synchronize()
+    return b
+
+
+def batch_leg(reco, torch, count):
+    """256 mixed-size reconstructions: one batched solve against the same
+    problems solved one at a time on the same GPU."""
+    import inputs
+    mix = inputs.batch_mix(count)
     t0 = time.perf_counter()
-    solvers.pcgls(W, b, fixed_iters=0, precond=M)      # initial W^T b and M^-1
-    t_init = time.perf_counter() - t0
+    geo = {}
+    for r in mix:
+        k = (r.side, r.n_angles)
+        if k not in geo:
+            geo[k] = reco.Geometry(r.side, r.n_angles, r.n_bins, inputs.default_levels(r.side),
+                                   reco.F32)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    gs = [geo[(r.side, r.n_angles)] for r in mix]
+    bs = [gpu_sinogram(torch, g, r.n_ellipses, r.seed, r.noise) for g, r in zip(gs, mix)]
+    xs = [g.new_image() for g in gs]
+    nnz = {k: g.count_nnz() for k, g in geo.items()}
+    # warm-up: a small batch and one solo solve of every geometry
+    reco.solve_batch(gs[:8], bs[:8], xs[:8], tol=1e-3)
+    seen = set()
+    for g, b, x, r in zip(gs, bs, xs, mix):
+        if (r.side, r.n_angles) not in seen:
+            seen.add((r.side, r.n_angles))
+            g.solve_cgls(b, x=x, tol=1e-3)
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
-    solvers.pcgls(W, b, fixed_iters=args.cpu_iters, precond=M)
-    t_k = time.perf_counter() - t0
-    per_iter = max((t_k - t_init) / args.cpu_iters, 1e-9)
-    return W.nnz, t_init, per_iter
+    infos = reco.solve_batch(gs, bs, xs, tol=1e-3)
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    solo_lat = []
+    for g, b, x in zip(gs, bs, xs):
+        s0 = time.perf_counter()
+        g.solve_cgls(b, x=x, tol=1e-3)
+        solo_lat.append((time.perf_counter() - s0) * 1e3)
+    torch.cuda.synchronize()
+    t_solo = time.perf_counter() - t0
+    its = [i["iters"] for i in infos]
+    updates = sum(2 * nnz[(r.side, r.n_angles)] * (i["iters"] + 0.5) for r, i in zip(mix, infos))
+    done_ms = sorted(i["elapsed_ms"] for i in infos)
+    return {
+        "workload": f"{count} reconstructions, side in {{128,256,512,1024}}, angles in "
+                    "{90,180,360,720}, bins ceil(side*sqrt2), 5-30 ellipses, 1% noise, "
+                    "WMG-CGLS to rel-res 1e-3",
+        "recons_per_s": round(count / t_batch, 3),
+        "seconds": round(t_batch, 4),
+        "solo_recons_per_s": round(count / t_solo, 3),
+        "solo_seconds": round(t_solo, 4),
+        "speedup_vs_solo": round(t_solo / t_batch, 3),
+        "all_ok": all(i["status"] == "ok" for i in infos),
+        "iters_min_max": [min(its), max(its)],
+        "gupdates_per_s": round(updates / t_batch / 1e9, 2),
+        "completion_ms_p50_p99": percentiles(done_ms),
+        "solo_latency_ms_p50_p99": percentiles(solo_lat),
+        "geometries": len(geo),
+        "setup_s": round(setup_s, 3),
+    }
+
+
+def serve_leg(reco, torch, count, rate, budget_gib, slots):
+    """Poisson arrivals into the continuous-batching server; the same requests
+    solved one at a time on the same GPU give the solo baseline."""
+    import threading
+    import inputs
+    mix = inputs.serving_mix(count, rate)
+    geo = {}
+    for r in mix:
+        k = (r.side, r.n_angles)
+        if k not in geo:
+            geo[k] = reco.Geometry(r.side, r.n_angles, r.n_bins, inputs.default_levels(r.side),
+                                   reco.F32)
+    gs = [geo[(r.side, r.n_angles)] for r in mix]
+    bs = [gpu_sinogram(torch, g, r.n_ellipses, r.seed, r.noise) for g, r in zip(gs, mix)]
+    xs = [g.new_image() for g in gs]
+    # solo baseline: each request alone in arrival order; the first request of a
+    # geometry also pays for building it (tables and packet diagonal), as in
+    # the server
+    solo_ms, built = [], set()
+    for g, b, x, r in zip(gs, bs, xs, mix):
+        torch.cuda.synchronize()
+        s0 = time.perf_counter()
+        if (r.side, r.n_angles) not in built:
+            built.add((r.side, r.n_angles))
+            reco.Geometry(r.side, r.n_angles, r.n_bins, inputs.default_levels(r.side), reco.F32)
+        g.solve_cgls(b, x=x, tol=r.tol)
+        torch.cuda.synchronize()
+        solo_ms.append((time.perf_counter() - s0) * 1e3)
+    # one-at-a-time FIFO server fed the same arrivals, from the measured solo times
+    fifo_lat, free_at = [], 0.0
+    for r, ms in zip(mix, solo_ms):
+        start = max(free_at, r.arrival_s)
+        free_at = start + ms * 1e-3
+        fifo_lat.append((free_at - r.arrival_s) * 1e3)
+    srv = reco.Server(int(budget_gib * (1 << 30)), max_slots=slots)
+    tickets = [None] * count
+    outs = [g.new_image() for g in gs]
+    t_start = reco.clock() + 0.05
+
+    def submitter():
+        for i, r in enumerate(mix):
+            dt = t_start + r.arrival_s - reco.clock()
+            if dt > 0:
+                time.sleep(dt)
+            tickets[i] = srv.submit(r.side, r.n_angles, r.n_bins, inputs.default_levels(r.side),
+                                    bs[i], outs[i], tol=r.tol)
+
+    th = threading.Thread(target=submitter)
+    th.start()
+    res = [None] * count
+    while any(v is None for v in res):
+        for i in range(count):
+            if res[i] is None and tickets[i] is not None:
+                res[i] = srv.poll(tickets[i])
+        time.sleep(0.0005)
+    th.join()
+    srv.close()
+    lat = [(v["t_done"] - v["t_submit"]) * 1e3 for v in res]
+    span = max(v["t_done"] for v in res) - min(v["t_submit"] for v in res)
+    same = all(torch.equal(a, b) for a, b in zip(outs, xs))
+    return {
+        "workload": f"{count} requests, Poisson arrivals at {rate}/s, side 256/512/1024/2048 "
+                    "at 40/30/20/10%, angles side/2..1.5 side, tol 1e-2 or 1e-3, 1% noise",
+        "recons_per_s": round(count / span, 3),
+        "latency_ms_p50_p99": percentiles(lat),
+        "queue_ms_p50_p99": percentiles([(v["t_admit"] - v["t_submit"]) * 1e3 for v in res]),
+        "all_ok": all(v["status"] == "ok" for v in res),
+        "results_equal_solo": bool(same),
+        "solo_fifo_latency_ms_p50_p99": percentiles(fifo_lat),
+        "solo_recons_per_s_busy": round(count / (sum(solo_ms) * 1e-3), 3),
+        "budget_gib": budget_gib, "max_slots": slots,
+        "geometries_built": len(built),
+        "note": "solo FIFO latency: a one-at-a-time server fed the same arrivals, computed "
+                "from each request's measured solo service time (geometry build on first use "
+                "plus the solve)",
+    }
+
+
+def ct2048_leg(reco, torch):
+    """2048^2 image, 2048 angles x 2897 bins, 5-level WMG-CGLS to rel-res 1e-3."""
+    t0 = time.perf_counter()
+    g = reco.Geometry(2048, 2048, 2897, 5, reco.F32)
+    torch.cuda.synchronize()
+    setup_ms = (time.perf_counter() - t0) * 1e3
+    nnz = g.count_nnz()
+    b = gpu_sinogram(torch, g, 40, 2000, 0.005)
+    x = g.new_image()
+    g.solve_cgls(b, x=x, tol=1e-3)          # warm-up
+    torch.cuda.synchronize()
+    reco.timing_reset()
+    reco.timing_enable(True)
+    t0 = time.perf_counter()
+    reps = 2
+    infos = [g.solve_cgls(b, x=x, tol=1e-3)[1] for _ in range(reps)]
+    torch.cuda.synchronize()
+    t = (time.perf_counter() - t0) / reps
+    kt = reco.timing_read()
+    reco.timing_enable(False)
+    it = sum(i["iters"] for i in infos)
+    fwd = nnz * it / (kt["forward"][1] * 1e-3) / 1e9
+    bwd = nnz * (it + reps) / (kt["backward"][1] * 1e-3) / 1e9
+    return {
+        "workload": "ct2048: 2048x2048 image, 2048 angles x 2897 bins, 40-ellipse phantom, "
+                    "0.5% noise, 5-level WMG-CGLS to rel-res 1e-3",
+        "recons_per_s": round(1.0 / t, 4), "ms_per_recon": round(t * 1e3, 2),
+        "iters": infos[0]["iters"], "status": infos[0]["status"],
+        "A_gupdates_per_s": round(fwd, 2), "AT_gupdates_per_s": round(bwd, 2),
+        "A_frac_of_alu_peak": round(fwd / (PEAK_VALU_LANE_OPS / ALG_OPS_PER_UPDATE / 1e9), 4),
+        "AT_frac_of_alu_peak": round(bwd / (PEAK_VALU_LANE_OPS / ALG_OPS_PER_UPDATE / 1e9), 4),
+        "kernel_avg_ms": {k: round(ms / n, 4) for k, (n, ms) in kt.items() if n},
+        "nnz": nnz, "setup_ms": round(setup_ms, 2),
+    }
 
 
 def main():
@@ -148,7 +353,14 @@ def main():
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     if args.profile_only:
-        print(json.dumps({"steps": args.steps, "seconds": elapsed}))
+        # Calibration for the HBM byte counters: plain device copies of a known
+        # size (read COPY_BYTES, write COPY_BYTES) in the same profiled process.
+        src = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"steps": args.steps, "seconds": elapsed, "copy_bytes": COPY_BYTES}))
         return
 
     # Same steps again with per-kernel HIP-event timing on the launch stream.
@@ -159,25 +371,30 @@ def main():
     torch.cuda.synchronize()
     kt = reco.timing_read()
     reco.timing_enable(False)
+    work_iters = sum(iters)
+    # Launches that did work: the forward projector runs once per iteration,
+    # the backprojector once per iteration plus once at the start of a solve.
+    # A launch issued after the device marked the solve finished returns at
+    # once; its (short) duration still counts in the totals below.
+    working = {"forward": work_iters, "backward": work_iters + args.steps}
     avg_ms = {k: (ms / n if n else 0.0) for k, (n, ms) in kt.items()}
+    gups = {k: nnz * working[k] / (kt[k][1] * 1e-3) / 1e9 for k in working if kt[k][1] > 0}
     dom = "forward" if kt["forward"][1] >= kt["backward"][1] else "backward"
-    # the solver launches the projector once per iteration on the current direction
-    gups = {k: nnz / (avg_ms[k] * 1e-3) / 1e9 for k in ("forward", "backward") if avg_ms[k] > 0}
-    peak = {k: PEAK_VALU_LANE_OPS / ALG_OPS_PER_UPDATE / 1e9 for k in ("forward", "backward")}
+    peak = PEAK_VALU_LANE_OPS / ALG_OPS_PER_UPDATE / 1e9
     N, M = w["n"] ** 2, w["m"] * w["nb"]
     spmv_bytes = 8.0 * nnz + 4.0 * (N + M)
-    src = {"forward": "project.hip", "backward": "backproject.hip"}[dom]
     roofline = {
         "bound": "alu",
         "kernel": dom,
         "achieved": round(gups[dom], 3),
-        "peak": round(peak[dom], 3),
+        "peak": round(peak, 3),
         "unit": "Gupdate/s",
-        "frac": round(gups[dom] / peak[dom], 4),
-        "traffic": traffic_for(src),
+        "frac": round(gups[dom] / peak, 4),
+        "traffic": traffic_for(dom),
         "avg_launch_ms": round(avg_ms[dom], 5),
         "launches": kt[dom][0],
-        "updates_per_launch": nnz,
+        "working_launches": working[dom],
+        "updates_per_working_launch": nnz,
         "alg_valu_ops_per_update": ALG_OPS_PER_UPDATE,
     }
     result = {
@@ -205,23 +422,28 @@ def main():
         "setup_ms": round(setup_ms, 3),
         "A_gupdates_per_s": round(gups.get("forward", 0.0), 3),
         "AT_gupdates_per_s": round(gups.get("backward", 0.0), 3),
-        "A_spmv_equiv_GBs": round(spmv_bytes / (avg_ms["forward"] * 1e-3) / 1e9, 1) if avg_ms["forward"] else None,
+        "A_spmv_equiv_GBs": round(spmv_bytes * gups.get("forward", 0.0) / nnz, 1),
         "kernel_avg_ms": {k: round(v, 5) for k, v in avg_ms.items()},
         "roofline": roofline,
     }
+    if args.batch > 0:
+        result["batch"] = batch_leg(reco, torch, args.batch)
+    if args.serve > 0:
+        result["serving"] = serve_leg(reco, torch, args.serve, args.serve_rate,
+                                      args.serve_budget_gib, args.serve_slots)
+    if not args.no_ct2048:
+        result["ct2048"] = ct2048_leg(reco, torch)
     if not args.no_cpu_baseline:
-        nnz_cpu, t_init, per_iter = cpu_baseline(args)
-        k = float(np.mean(iters))
-        t_recon = t_init + k * per_iter
+        solved, t_sum, cpu_iters = cpu_baseline(args)
         result["cpu_baseline"] = {
-            "value": round(1.0 / t_recon, 5),
+            "value": round(solved / t_sum, 5),
             "unit": "recons/s",
             "cores": 1,
             "kind": "oracle",
-            "sample": f"float64 scipy-CSR oracle, WMG-CGLS on the same 512^2 workload: initial "
-                      f"step + {args.cpu_iters} iterations timed ({t_init:.2f} s + "
-                      f"{per_iter:.3f} s/iter), scaled to the GPU's {k:.1f} iterations per "
-                      f"reconstruction; matrix assembly and packet diagonal excluded as setup",
+            "sample": f"{solved} whole float64 oracle WMG-CGLS reconstructions of the same "
+                      f"512^2 workload (scipy CSR matrix, single thread) to rel-res 1e-3 in "
+                      f"{t_sum:.2f} s, {cpu_iters} iterations; matrix assembly and packet "
+                      f"diagonal excluded as setup",
         }
     print(json.dumps(result), flush=True)
 

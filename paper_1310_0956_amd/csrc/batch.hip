@@ -407,6 +407,10 @@ reco_status solve_batch(int32_t count, const reco_geometry* geoms, const void* c
 // ---------------------------------------------------------------------------
 // Server: continuous batching with admission by device-memory budget
 // ---------------------------------------------------------------------------
+// Threads: the caller's (submit / poll), the scheduler (admission, ticks of
+// the batched engine on the server's stream) and a geometry builder (tables
+// and packet diagonal of descriptions seen for the first time, on a stream
+// of its own, so that running requests keep advancing meanwhile).
 namespace {
 
 struct Request {
@@ -427,11 +431,15 @@ struct Request {
 using DescKey = std::tuple<int, int, int, int, int>;
 
 struct GeoEntry {
+  reco_geometry_desc desc{};
   Geometry* g = nullptr;
+  bool building = false;
+  reco_status err = RECO_OK;
+  std::string err_msg;
   size_t bytes = 0;
   size_t ws_bytes = 0;   // bytes of one workspace
-  int running = 0;       // requests using it now
-  int workspaces = 0;    // workspaces it holds (running + pooled)
+  int running = 0;       // admitted requests using it
+  int workspaces = 0;    // workspaces it holds or will hold (admitted + pooled)
 };
 
 DescKey key_of(const reco_geometry_desc& d) {
@@ -449,15 +457,19 @@ struct Server {
   std::deque<Request*> queue;
   std::unordered_map<uint64_t, std::unique_ptr<Request>> all;
   uint64_t next_ticket = 1;
-  bool stop = false;
-  std::thread th;
-  // scheduler-thread state (guarded by mu where shared)
+  uint64_t submits = 0, builds = 0;   // change counters the scheduler waits on
+  bool stop = false, stop_builder = false;
+  std::thread th, builder;
   std::map<DescKey, GeoEntry> geos;
-  size_t used = 0;   // geometries + workspaces held
-  int running = 0;
+  std::deque<DescKey> to_build;
+  std::vector<Request*> waiting;      // admitted, geometry not built yet
+  size_t used = 0;                    // geometries + workspaces held
+  int running = 0;                    // admitted requests
 
   void run();
+  void build_loop();
   void finish(Request* r, reco_status st, const std::string& err);
+  void release(Request* r);
   bool make_room(size_t need);
 };
 
@@ -471,7 +483,19 @@ void Server::finish(Request* r, reco_status st, const std::string& err) {
   r->t[2] = seconds_now();
 }
 
+// Undo the admission accounting of a request that never ran.  Lock held.
+void Server::release(Request* r) {
+  const DescKey k = key_of(r->desc);
+  GeoEntry& e = geos[k];
+  used -= r->need;
+  --running;
+  --e.running;
+  if (r->fresh_ws) --e.workspaces;
+  if (!e.g && !e.building && e.running == 0) geos.erase(k);
+}
+
 // Free pooled workspaces and unused geometries until `need` more bytes fit.
+// Lock held.
 bool Server::make_room(size_t need) {
   if (used + need <= budget) return true;
   for (auto& kv : geos) {
@@ -484,11 +508,12 @@ bool Server::make_room(size_t need) {
     }
   }
   for (auto it = geos.begin(); it != geos.end() && used + need > budget;) {
-    if (it->second.running == 0) {
-      used -= it->second.bytes;
-      if (it->second.g) {
-        release_workspaces(*it->second.g);
-        delete it->second.g;
+    GeoEntry& e = it->second;
+    if (e.running == 0 && !e.building) {
+      used -= e.bytes;
+      if (e.g) {
+        release_workspaces(*e.g);
+        delete e.g;
       }
       it = geos.erase(it);
     } else {
@@ -496,6 +521,53 @@ bool Server::make_room(size_t need) {
     }
   }
   return used + need <= budget;
+}
+
+void Server::build_loop() {
+  (void)hipSetDevice(device);
+  hipStream_t st = nullptr;
+  std::string fatal;
+  if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
+    (void)hipGetLastError();
+    fatal = "could not create the geometry builder's stream";
+  }
+  for (;;) {
+    reco_geometry_desc d{};
+    DescKey k;
+    {
+      std::unique_lock<std::mutex> lk(mu);
+      cv.wait(lk, [&] { return stop_builder || !to_build.empty(); });
+      if (to_build.empty()) break;
+      k = to_build.front();
+      to_build.pop_front();
+      d = geos[k].desc;
+    }
+    Geometry* g = nullptr;
+    reco_status err = RECO_OK;
+    std::string msg;
+    if (!fatal.empty()) {
+      err = RECO_EDEVICE;
+      msg = fatal;
+    } else {
+      try {
+        g = create_geometry(d, st);
+      } catch (const Error& e) {
+        err = e.code;
+        msg = e.msg;
+      }
+    }
+    {
+      std::lock_guard<std::mutex> lk(mu);
+      GeoEntry& e = geos[k];
+      e.building = false;
+      e.g = g;
+      e.err = err;
+      e.err_msg = msg;
+      ++builds;
+    }
+    cv.notify_all();
+  }
+  if (st) (void)hipStreamDestroy(st);
 }
 
 void Server::run() {
@@ -510,8 +582,10 @@ void Server::run() {
     fatal = e.msg;
   }
   std::vector<Request*> active;
+  uint64_t seen_submits = ~0ull, seen_builds = ~0ull;
+  bool retired = false;   // the last tick freed slots or memory
   for (;;) {
-    std::vector<Request*> admit;
+    std::vector<Request*> ready;
     {
       std::unique_lock<std::mutex> lk(mu);
       if (!fatal.empty()) {
@@ -521,12 +595,17 @@ void Server::run() {
         cv.wait(lk, [&] { return stop || !queue.empty(); });
         continue;
       }
-      if (active.empty() && queue.empty()) {
-        if (stop) break;
-        cv.wait(lk, [&] { return stop || !queue.empty(); });
+      const bool changed = retired || seen_submits != submits || seen_builds != builds;
+      seen_submits = submits;
+      seen_builds = builds;
+      retired = false;
+      if (active.empty() && !changed) {
+        if (stop && queue.empty() && waiting.empty()) break;
+        cv.wait(lk, [&] { return stop || submits != seen_submits || builds != seen_builds; });
         continue;
       }
       // admit in arrival order while slots and memory allow
+      bool new_builds = false;
       while (!queue.empty() && running < max_slots) {
         Request* r = queue.front();
         const DescKey k = key_of(r->desc);
@@ -551,8 +630,15 @@ void Server::run() {
         queue.pop_front();
         GeoEntry& e = geos[k];
         if (e.ws_bytes == 0) {
+          e.desc = r->desc;
           e.bytes = geometry_bytes(r->desc);
           e.ws_bytes = cgls_workspace_bytes(r->desc);
+        }
+        if (!e.g && !e.building) {
+          e.building = true;
+          e.err = RECO_OK;
+          to_build.push_back(k);
+          new_builds = true;
         }
         r->fresh_ws = e.workspaces - e.running <= 0;
         if (r->fresh_ws) ++e.workspaces;
@@ -560,22 +646,37 @@ void Server::run() {
         r->need = need;
         used += need;
         ++running;
-        admit.push_back(r);
+        waiting.push_back(r);
       }
+      if (new_builds) cv.notify_all();
+      // requests whose geometry is ready (or failed) leave the waiting list
+      std::vector<Request*> still;
+      for (Request* r : waiting) {
+        GeoEntry& e = geos[key_of(r->desc)];
+        if (e.g) {
+          ready.push_back(r);
+        } else if (!e.building) {
+          const reco_status code = e.err != RECO_OK ? e.err : RECO_EDEVICE;
+          const std::string msg = e.err_msg;
+          release(r);
+          finish(r, code, msg.empty() ? "geometry creation failed" : msg);
+        } else {
+          still.push_back(r);
+        }
+      }
+      waiting.swap(still);
     }
-    // create geometries and check out workspaces outside the lock
+    // check out workspaces outside the lock
     std::vector<Slot*> slots;
-    for (Request* r : admit) {
-      const DescKey k = key_of(r->desc);
-      GeoEntry* e;
+    for (Request* r : ready) {
+      Geometry* g;
       {
         std::lock_guard<std::mutex> lk(mu);
-        e = &geos[k];
+        g = geos[key_of(r->desc)].g;
       }
       try {
-        if (!e->g) e->g = create_geometry(r->desc, st);
-        r->slot.g = e->g;
-        r->slot.w = checkout_workspace(*e->g, st);
+        r->slot.g = g;
+        r->slot.w = checkout_workspace(*g, st);
         r->slot.b = r->b;
         r->slot.x = r->x;
         r->slot.o = r->o;
@@ -587,18 +688,16 @@ void Server::run() {
         active.push_back(r);
       } catch (const Error& err) {
         std::lock_guard<std::mutex> lk(mu);
-        used -= r->need;
-        --running;
-        --e->running;
-        if (r->fresh_ws) --e->workspaces;
-        if (!e->g && e->running == 0) geos.erase(k);
+        release(r);
         finish(r, err.code, err.msg);
       }
     }
+    if (active.empty()) continue;
     try {
       eng->add(slots);
       std::vector<Slot*> done = eng->tick();
       std::lock_guard<std::mutex> lk(mu);
+      retired = !done.empty();
       for (Slot* s : done) {
         Request* r = (Request*)s->owner;
         GeoEntry& e = geos[key_of(r->desc)];
@@ -615,12 +714,20 @@ void Server::run() {
       std::lock_guard<std::mutex> lk(mu);
       fatal = err.msg;
       for (Request* r : active) finish(r, RECO_EDEVICE, fatal);
+      for (Request* r : waiting) finish(r, RECO_EDEVICE, fatal);
       active.clear();
-      running = 0;
+      waiting.clear();
     }
   }
+  {
+    std::lock_guard<std::mutex> lk(mu);
+    stop_builder = true;
+  }
+  cv.notify_all();
+  if (builder.joinable()) builder.join();
   eng.reset();
   for (auto& kv : geos) {
+    if (!kv.second.g) continue;
     release_workspaces(*kv.second.g);
     delete kv.second.g;
   }
@@ -648,7 +755,18 @@ reco_status reco_server_create(size_t hbm_budget_bytes, int32_t max_slots, reco_
     s->max_slots = max_slots;
     reco::check_hip(hipGetDevice(&s->device), "hipGetDevice", __FILE__, __LINE__);
     reco::Server* p = s.get();
-    s->th = std::thread([p] { p->run(); });
+    s->builder = std::thread([p] { p->build_loop(); });
+    try {
+      s->th = std::thread([p] { p->run(); });
+    } catch (...) {
+      {
+        std::lock_guard<std::mutex> lk(p->mu);
+        p->stop_builder = true;
+      }
+      p->cv.notify_all();
+      p->builder.join();
+      throw;
+    }
     *out = reinterpret_cast<reco_server>(s.release());
     return RECO_OK;
   } catch (const reco::Error& e) {
@@ -700,6 +818,7 @@ reco_status reco_submit(reco_server h, const reco_geometry_desc* desc, const voi
       std::lock_guard<std::mutex> lk(s->mu);
       if (s->stop) reco::fail(RECO_EINVAL, "server is shutting down");
       r->ticket = s->next_ticket++;
+      ++s->submits;
       *ticket = r->ticket;
       s->queue.push_back(r.get());
       s->all[r->ticket] = std::move(r);
