@@ -147,8 +147,9 @@ reco_status reco_backproject(reco_geometry g, const void* b, void* x, void* stre
 reco_status reco_wmg_apply(reco_geometry g, const void* r, void* z, double lambda,
                            void* stream);
 
-/* CGLS on (W^T W + lambda I) x = W^T b (Section 2.2.1), preconditioned by
- * M^-1 when opts->precond == RECO_PRECOND_WMG.  b: sinogram; x: image, output
+/* CGLS on (W^T W + lambda I) x = W^T b (a Krylov method of Section 2.3.1),
+ * preconditioned by M^-1 when opts->precond == RECO_PRECOND_WMG.
+ * b: sinogram; x: image, output
  * (the solve starts from x = 0).  Synchronous: returns when done.
  * Returns RECO_OK, RECO_ENOTCONV (x = last iterate), RECO_ENUMERIC, or an
  * error; *info (may be NULL) receives the counts and final relres. */

@@ -3,8 +3,8 @@
 All solvers start from x0 = 0 (the paper's error definitions ||e_k||/||e_0|| and
 ||x_k - x_ex||/||x_ex|| in Tables 1 and 2 coincide only then).
 
-PCGLS (CGLS, Section 2.2.1, with a symmetric positive definite M^-1 applied
-to the normal equations K x = W^T b, K = W^T W + lam I, eq. sys_ne / sys_reg):
+PCGLS (CGLS, a Krylov method of Section 2.3.1, with a symmetric positive
+definite M^-1 applied to the normal equations K x = W^T b, K = W^T W + lam I, eq. sys_ne / sys_reg):
     x = 0, r = b, s = W^T r - lam x, z = M^-1 s, p = z, gamma = <s, z>
     repeat:
         q = W p;  delta = ||q||^2 + lam ||p||^2;  alpha = gamma / delta

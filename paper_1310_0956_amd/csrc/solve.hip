@@ -1,5 +1,5 @@
-// Solver drivers: CGLS (Section 2.2.1 with an SPD preconditioner on the normal
-// equations), restarted right-preconditioned GMRES (eq. sys_prec) and SIRT
+// Solver drivers: CGLS (a Krylov method, Section 2.3.1, with an SPD
+// preconditioner on the normal equations), restarted right-preconditioned GMRES (eq. sys_prec) and SIRT
 // (eq. sirt_it).  The Krylov state stays on the device; scalars are float64.
 // The host only enqueues iterations and polls a pinned copy of the device
 // state every few iterations; once the device marks the solve finished every
