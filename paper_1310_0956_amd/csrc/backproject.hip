@@ -4,7 +4,7 @@
 // waves (two pixels per thread), each looping over its share of the angle
 // chunks (32 angles each); their partial sums are added in group order at the
 // end (no atomics).  For each angle of a chunk the tile's
-// detector footprint (at most 24 bins for a 16-pixel tile) is staged in LDS,
+// detector footprint (at most 26 bins for a 16-pixel tile) is staged in LDS,
 // double buffered: the next chunk's window is fetched into registers while the
 // current one is consumed.  Every pixel then reads its two candidate
 // bins floor(J) and floor(J)+1, J being the bin coordinate of the pixel
@@ -22,7 +22,9 @@ namespace {
 constexpr int kTile = 16;    // pixels per tile side
 constexpr int kThreads = 128; // two pixels per thread: rows ty and ty + 8
 constexpr int kChunk = 32;    // angles per LDS stage
-constexpr int kWin = 32;      // bins staged per angle
+constexpr int kWin = 28;      // bins staged per angle: pixel centres lie within
+                              // 7.5 * sqrt(2) < 11 bins of the tile centre, so
+                              // floor(J) + 1 <= kHalf + 1 + 11 < kWin
 constexpr int kHalf = 12;     // window starts kHalf bins below the tile centre
 constexpr int kPerThread = kChunk * kWin / kThreads;
 
@@ -30,6 +32,13 @@ template <typename T>
 struct BwdK {
   const T* sino;
   T* out;
+  const T* q;        // CGLS: projected direction (residual step r - alpha q)
+  T* p;              // CGLS: direction
+  T* xo;             // CGLS: iterate (updated)
+  T* zP;             // CGLS: padded z
+  T* zTP;            // CGLS: padded transposed z
+  const T* d;        // CGLS: packet diagonal
+  int ld, L, identity, fuse;
   const T* xin;      // extra term source (plain or padded layout)
   const T* fin;      // residual form: right-hand side
   const T* C;        // SIRT: inverse column sums
@@ -68,9 +77,10 @@ __device__ __forceinline__ void fill_meta(Meta<T>& M, const BwdAngle& A, double 
 __device__ __forceinline__ float clampw(float v, float hi) { return __builtin_amdgcn_fmed3f(v, 0.0f, hi); }
 __device__ __forceinline__ double clampw(double v, double hi) { return fmin(fmax(v, 0.0), hi); }
 
-// One pixel, one angle: the two candidate bins floor(J), floor(J)+1 of the window.
+// One pixel, one angle: the two candidate bins floor(J), floor(J)+1 of the
+// window, accumulated into acc.
 template <typename T>
-__device__ __forceinline__ T pixel_term(T J, const T* __restrict__ w, const Meta<T>& M) {
+__device__ __forceinline__ T pixel_term(T J, const T* __restrict__ w, const Meta<T>& M, T acc) {
   const int j0 = (int)J;   // J > 0 inside the window: truncation is floor
   T f;
   if constexpr (sizeof(T) == 4) f = __builtin_amdgcn_fractf(J);
@@ -78,7 +88,102 @@ __device__ __forceinline__ T pixel_term(T J, const T* __restrict__ w, const Meta
   const T r0 = w[j0], r1 = w[j0 + 1];
   const T w0 = clampw(fma(f, -M.B, M.C0), M.Wm);
   const T w1 = clampw(fma(f, M.B, M.C1), M.Wm);
-  return fma(w0, r0, w1 * r1);
+  return fma(w0, r0, fma(w1, r1, acc));
+}
+
+// Raw window loads of one chunk: element e = t + kThreads*i of the chunk's
+// [kChunk][kWin] window.  Every load is issued unconditionally (from bin 0
+// for elements outside the sinogram, masked afterwards), so they are all in
+// flight together; in the CGLS modes the projected direction is loaded too.
+constexpr bool kCglsMode(int mode) { return mode == BWD_CGLS || mode == BWD_CGLS_INIT; }
+
+template <typename T, int MODE>
+struct Stage {
+  T r[kPerThread];
+  T q[kCglsMode(MODE) ? kPerThread : 1];
+  unsigned valid;
+};
+
+template <typename T, int MODE>
+__device__ __forceinline__ void stage_load(Stage<T, MODE>& sg, const BwdK<T>& a,
+                                           const Meta<T>* __restrict__ mt, int k0, int t) {
+  sg.valid = 0;
+#pragma unroll
+  for (int i = 0; i < kPerThread; ++i) {
+    const int e = t + kThreads * i, kk = e / kWin, jj = e % kWin;
+    const int j = mt[kk].jw + jj;
+    const bool ok = k0 + kk < a.m && j >= 0 && j < a.nb;
+    const size_t idx = ok ? (size_t)(k0 + kk) * a.nb + j : 0;
+    sg.r[i] = a.sino[idx];
+    if constexpr (kCglsMode(MODE)) sg.q[i] = a.q[idx];
+    sg.valid |= (ok ? 1u : 0u) << i;
+  }
+}
+
+// Window values: the sinogram operand, in the CGLS modes the residual after
+// the current step, r - alpha q (the forward projector of the next iteration
+// stores the same value).
+template <typename T, int MODE>
+__device__ __forceinline__ void stage_store(const Stage<T, MODE>& sg, T* __restrict__ w,
+                                            double alpha, int t) {
+#pragma unroll
+  for (int i = 0; i < kPerThread; ++i) {
+    T v = sg.r[i];
+    if constexpr (kCglsMode(MODE)) v = (T)((double)sg.r[i] - alpha * (double)sg.q[i]);
+    w[t + kThreads * i] = ((sg.valid >> i) & 1u) ? v : T(0);
+  }
+}
+
+// Walsh-Hadamard transform of every 2^L x 2^L tile of a 16 x 16 LDS tile
+// (the full Haar packet transform up to the 2^-L scale): butterflies along x,
+// then along y, one pair per thread for the first 128 threads, one barrier per
+// stage.  All threads of the block must call it.
+template <typename T, int L>
+__device__ __forceinline__ void wht16(T (*tile)[kTile + 1]) {
+  const int t = threadIdx.x;
+#pragma unroll
+  for (int b = 0; b < L; ++b) {
+    if (t < 128) {
+      const int row = t >> 3, pi = t & 7;
+      const int xa = ((pi >> b) << (b + 1)) | (pi & ((1 << b) - 1)), xb = xa | (1 << b);
+      const T u = tile[row][xa], v = tile[row][xb];
+      tile[row][xa] = u + v;
+      tile[row][xb] = u - v;
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int b = 0; b < L; ++b) {
+    if (t < 128) {
+      const int col = t & 15, pi = t >> 4;
+      const int ya = ((pi >> b) << (b + 1)) | (pi & ((1 << b) - 1)), yb = ya | (1 << b);
+      const T u = tile[ya][col], v = tile[yb][col];
+      tile[ya][col] = u + v;
+      tile[yb][col] = u - v;
+    }
+    __syncthreads();
+  }
+}
+
+// z = H^T diag(4^-L / (d + lambda)) H s on the 16 x 16 tile at (x0, y0),
+// in place (1/0 := 0).  Threads t < 256 own pixel (t & 15, t >> 4).
+template <typename T, int L>
+__device__ __forceinline__ void wmg_tile(T (*tile)[kTile + 1], const T* __restrict__ d, int n,
+                                         int x0, int y0, double lambda) {
+  wht16<T, L>(tile);
+  const int t = threadIdx.x;
+  if (t < kTile * kTile) {
+    const int px = t & (kTile - 1), py = t / kTile;
+    const int ix = x0 + px, iy = y0 + py;
+    double inv = 0.0;
+    if (ix < n && iy < n) {
+      const double dd = (double)d[(size_t)iy * n + ix] + lambda;
+      inv = dd != 0.0 ? (1.0 / (double)(1u << (2 * L))) / dd : 0.0;
+    }
+    tile[py][px] = (T)((double)tile[py][px] * inv);
+  }
+  __syncthreads();
+  wht16<T, L>(tile);
 }
 
 // Angle groups per block: group g handles the chunks c = g, g + G, ...; the G
@@ -90,9 +195,18 @@ template <typename T, int MODE>
 __device__ __forceinline__ void backward_body(const BwdK<T>& a, const BlockPos pos) {
   constexpr int G = kGroups<T>;
   if (a.st && a.st->done) return;   // solver finished: later launches are no-ops
+  // CGLS: this iteration's step length and the previous direction coefficient
+  // (the last block overwrites beta only after every block has read it)
+  double alpha = 0.0, beta = 0.0;
+  if constexpr (MODE == BWD_CGLS || MODE == BWD_CGLS_INIT) {
+    alpha = a.st->alpha;
+    beta = a.st->beta;
+  }
   __shared__ T win[G][2][kChunk * kWin];
   __shared__ Meta<T> meta[G][2][kChunk];
-  __shared__ T part[G][2][kThreads];
+  // the groups' partial sums reuse the window memory once the angle loop is done
+  static_assert(G * 2 * kThreads <= G * 2 * kChunk * kWin, "partials must fit in the window");
+  T (*part)[2][kThreads] = reinterpret_cast<T (*)[2][kThreads]>(&win[0][0][0]);
   const int grp = __builtin_amdgcn_readfirstlane((int)threadIdx.x / kThreads);
   const int t = threadIdx.x - grp * kThreads;
   const int tx = t & (kTile - 1), ty = t / kTile;          // ty in [0, 8)
@@ -111,16 +225,9 @@ __device__ __forceinline__ void backward_body(const BwdK<T>& a, const BlockPos p
     const int k0 = grp * kChunk;
     if (t < kChunk && k0 + t < m) fill_meta<T>(meta[grp][0][t], a.ang[k0 + t], Xc, Yc, hb);
     __syncthreads();
-#pragma unroll
-    for (int i = 0; i < kPerThread; ++i) {
-      const int e = t + kThreads * i, kk = e / kWin, jj = e % kWin;
-      T v = T(0);
-      if (k0 + kk < m) {
-        const int j = meta[grp][0][kk].jw + jj;
-        if (j >= 0 && j < nb) v = a.sino[(size_t)(k0 + kk) * nb + j];
-      }
-      win[grp][0][e] = v;
-    }
+    Stage<T, MODE> sg;
+    stage_load<T, MODE>(sg, a, meta[grp][0], k0, t);
+    stage_store<T, MODE>(sg, win[grp][0], alpha, t);
     __syncthreads();
   }
   for (int st = 0; st < steps; ++st) {
@@ -129,21 +236,12 @@ __device__ __forceinline__ void backward_body(const BwdK<T>& a, const BlockPos p
     const int k0 = c * kChunk, kc = max(0, min(kChunk, m - k0));
     const int k1 = k0 + G * kChunk;              // its next chunk
     const bool more = st + 1 < steps;
-    // stage the next chunk's constants, then start its window loads
+    // stage the next chunk's constants, then start its window loads; they
+    // are consumed after the current chunk is done
     if (more && t < kChunk && k1 + t < m) fill_meta<T>(meta[grp][nxt][t], a.ang[k1 + t], Xc, Yc, hb);
     __syncthreads();
-    T pre[kPerThread];
-    if (more) {
-#pragma unroll
-      for (int i = 0; i < kPerThread; ++i) {
-        const int e = t + kThreads * i, kk = e / kWin, jj = e % kWin;
-        pre[i] = T(0);
-        if (k1 + kk < m) {
-          const int j = meta[grp][nxt][kk].jw + jj;
-          if (j >= 0 && j < nb) pre[i] = a.sino[(size_t)(k1 + kk) * nb + j];
-        }
-      }
-    }
+    Stage<T, MODE> pre;
+    if (more) stage_load<T, MODE>(pre, a, meta[grp][nxt], k1, t);
     // compute the current chunk
 #pragma unroll 4
     for (int kk = 0; kk < kc; ++kk) {
@@ -151,13 +249,10 @@ __device__ __forceinline__ void backward_body(const BwdK<T>& a, const BlockPos p
       const T* w = win[grp][cur] + kk * kWin;
       const T Ja = fma(dX, M.c, fma(dY, M.s, M.base));
       const T Jb = fma(T(8), M.s, Ja);
-      acc0 += pixel_term<T>(Ja, w, M);
-      acc1 += pixel_term<T>(Jb, w, M);
+      acc0 = pixel_term<T>(Ja, w, M, acc0);
+      acc1 = pixel_term<T>(Jb, w, M, acc1);
     }
-    if (more) {
-#pragma unroll
-      for (int i = 0; i < kPerThread; ++i) win[grp][nxt][t + kThreads * i] = pre[i];
-    }
+    if (more) stage_store<T, MODE>(pre, win[grp][nxt], alpha, t);
     __syncthreads();
   }
   part[grp][0][t] = acc0;
@@ -174,6 +269,76 @@ __device__ __forceinline__ void backward_body(const BwdK<T>& a, const BlockPos p
     }
   }
   const int iys[2] = {iy0, iy1};
+  if constexpr (MODE == BWD_CGLS || MODE == BWD_CGLS_INIT) {
+    // s = W^T r - lambda x for the tile's pixels, after p = z + beta p and
+    // x += alpha p; then z = M^-1 s on the tile and the four dot products.
+    T* lds = &win[0][0][0] + G * 2 * kThreads;   // past the partial sums
+    T (*stile)[kTile + 1] = reinterpret_cast<T (*)[kTile + 1]>(lds);
+    T (*ptile)[kTile + 1] = reinterpret_cast<T (*)[kTile + 1]>(lds + kTile * (kTile + 1));
+    const double lambda = a.st->lambda;
+    const int x0 = pos.x * kTile, y0 = pos.y * kTile;
+    if (grp == 0) {
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        const int ly = ty + 8 * q, iy = iys[q];
+        T sv = T(0), pv = T(0);
+        if (ix < n && iy < n) {
+          const size_t px = (size_t)iy * n + ix;
+          T xn;
+          if constexpr (MODE == BWD_CGLS) {
+            const double z = (double)a.zP[(size_t)iy * a.ld + ix + kPad];
+            pv = (T)(z + beta * (double)a.p[px]);
+            a.p[px] = pv;
+            xn = (T)((double)a.xo[px] + alpha * (double)pv);
+            a.xo[px] = xn;
+          } else {
+            xn = a.xo[px];
+          }
+          sv = (T)(bp[q] - lambda * (double)xn);
+          if (!a.fuse) a.out[px] = sv;
+        }
+        stile[ly][tx] = sv;
+        ptile[ly][tx] = pv;
+      }
+    }
+    if (!a.fuse) return;   // uniform: the WMG apply runs as its own launch
+    __syncthreads();
+    const int tt = threadIdx.x;
+    const int qx = tt & (kTile - 1), qy = tt / kTile;   // pixel of threads tt < 256
+    T s_own = T(0), p_own = T(0);
+    if (tt < kTile * kTile) {
+      s_own = stile[qy][qx];
+      p_own = ptile[qy][qx];
+    }
+    __syncthreads();
+    if (!a.identity) {
+      switch (a.L) {
+        case 0: wmg_tile<T, 0>(stile, a.d, n, x0, y0, lambda); break;
+        case 1: wmg_tile<T, 1>(stile, a.d, n, x0, y0, lambda); break;
+        case 2: wmg_tile<T, 2>(stile, a.d, n, x0, y0, lambda); break;
+        case 3: wmg_tile<T, 3>(stile, a.d, n, x0, y0, lambda); break;
+        default: wmg_tile<T, 4>(stile, a.d, n, x0, y0, lambda); break;
+      }
+    }
+    double v[4] = {0.0, 0.0, 0.0, 0.0};   // <s,z>, ||s||^2, ||z||^2, <z,p>
+    if (tt < kTile * kTile) {
+      const T z = stile[qy][qx];
+      if (x0 + qx < n && y0 + qy < n) a.zP[(size_t)(y0 + qy) * a.ld + x0 + qx + kPad] = z;
+      // transposed copy: consecutive threads write consecutive addresses
+      if (x0 + qy < n && y0 + qx < n) a.zTP[(size_t)(x0 + qy) * a.ld + y0 + qx + kPad] = stile[qx][qy];
+      const double sd = (double)s_own, zd = (double)z;
+      v[0] = sd * zd;
+      v[1] = sd * sd;
+      v[2] = zd * zd;
+      if (MODE == BWD_CGLS && lambda != 0.0) v[3] = zd * (double)p_own;
+    }
+    SolverState* sst = a.st;
+    reduce_and_finish<4, kThreads * G / 64>(v, a.red, pos.count(), pos.id(),
+                                            [sst](double (&tot)[4]) {
+                                              cgls_precond_finish(sst, tot, MODE == BWD_CGLS_INIT);
+                                            });
+    return;
+  }
   if constexpr (MODE == BWD_SIRT) {
     double usq = 0.0;
     if (grp == 0) {
@@ -223,9 +388,6 @@ __device__ __forceinline__ void backward_body(const BwdK<T>& a, const BlockPos p
       const size_t p = (size_t)iy * n + ix;
       if constexpr (MODE == BWD_PLAIN) {
         a.out[p] = (T)bp[q];
-      } else if constexpr (MODE == BWD_CGLS) {
-        // s = W^T r - lambda x
-        a.out[p] = (T)(bp[q] - a.st->lambda * (double)a.xin[p]);
       } else if constexpr (MODE == BWD_AXPY) {
         double v = a.sa * bp[q];
         if (a.sx != 0.0) v += a.sx * (double)a.xin[(size_t)iy * a.x_ld + ix + a.x_off];
@@ -236,13 +398,18 @@ __device__ __forceinline__ void backward_body(const BwdK<T>& a, const BlockPos p
   }
 }
 
+// Four blocks per CU (the LDS limit) need 8 waves per SIMD for float blocks of
+// 8 waves: at most 64 VGPRs.
+template <typename T>
+constexpr int kMinWaves = sizeof(T) == 4 ? 8 : 4;
+
 template <typename T, int MODE>
-__global__ __launch_bounds__(kThreads * kGroups<T>) void k_backward(BwdK<T> a) {
+__global__ __launch_bounds__(kThreads * kGroups<T>, kMinWaves<T>) void k_backward(BwdK<T> a) {
   backward_body<T, MODE>(a, grid_pos());
 }
 
 template <typename T, int MODE>
-__global__ __launch_bounds__(kThreads * kGroups<T>) void k_backward_batch(
+__global__ __launch_bounds__(kThreads * kGroups<T>, kMinWaves<T>) void k_backward_batch(
     const BwdK<T>* __restrict__ args, const int* __restrict__ start, const int* __restrict__ gx,
     int count) {
   const int r = batch_find(start, count, blockIdx.x);
@@ -254,6 +421,16 @@ BwdK<T> bwd_args(const Geometry& g, const BwdArgs& a) {
   BwdK<T> k;
   k.sino = (const T*)a.sino;
   k.out = (T*)a.out;
+  k.q = (const T*)a.q;
+  k.p = (T*)a.p;
+  k.xo = (T*)a.x;
+  k.zP = (T*)a.zP;
+  k.zTP = (T*)a.zTP;
+  k.d = (const T*)g.d_diag;
+  k.ld = g.ld;
+  k.L = g.L;
+  k.identity = a.identity ? 1 : 0;
+  k.fuse = backward_fuses_wmg(g) ? 1 : 0;
   k.xin = (const T*)a.x;
   k.fin = (const T*)a.f;
   k.C = (const T*)a.C;
@@ -283,11 +460,16 @@ void bwd_dispatch(const Geometry& g, BwdMode mode, const BwdArgs& a, hipStream_t
     case BWD_CGLS: hipLaunchKernelGGL((k_backward<T, BWD_CGLS>), grid, block, 0, st, k); break;
     case BWD_SIRT: hipLaunchKernelGGL((k_backward<T, BWD_SIRT>), grid, block, 0, st, k); break;
     case BWD_AXPY: hipLaunchKernelGGL((k_backward<T, BWD_AXPY>), grid, block, 0, st, k); break;
+    case BWD_CGLS_INIT:
+      hipLaunchKernelGGL((k_backward<T, BWD_CGLS_INIT>), grid, block, 0, st, k);
+      break;
   }
   HIP_CHECK(hipGetLastError());
 }
 
 }  // namespace
+
+bool backward_fuses_wmg(const Geometry& g) { return (1 << g.L) <= kTile; }
 
 int backward_blocks(const Geometry& g) {
   const int t = (g.n + kTile - 1) / kTile;
@@ -321,6 +503,10 @@ void launch_backward_batch(const DevTable& t, BwdMode mode, hipStream_t st) {
     case BWD_CGLS:
       hipLaunchKernelGGL((k_backward_batch<float, BWD_CGLS>), dim3(t.total_blocks), block, 0, st,
                          args, t.start, t.gx, t.count);
+      break;
+    case BWD_CGLS_INIT:
+      hipLaunchKernelGGL((k_backward_batch<float, BWD_CGLS_INIT>), dim3(t.total_blocks), block, 0,
+                         st, args, t.start, t.gx, t.count);
       break;
     case BWD_PLAIN:
       hipLaunchKernelGGL((k_backward_batch<float, BWD_PLAIN>), dim3(t.total_blocks), block, 0, st,

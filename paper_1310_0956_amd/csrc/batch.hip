@@ -129,7 +129,7 @@ class Engine {
   // add them to the work lists from the next tick on.
   void add(const std::vector<Slot*>& slots) {
     if (slots.empty()) return;
-    std::vector<const Geometry*> gs;
+    std::vector<const Geometry*> gs, gw;
     std::vector<InitArgs> ia;
     std::vector<BwdArgs> ba;
     std::vector<WmgArgs> wa;
@@ -154,13 +154,16 @@ class Engine {
       i.hist_cap = s->limit;
       ia.push_back(i);
       ba.push_back(bwd_of(*s));
-      wa.push_back(wmg_of(*s));
+      if (!backward_fuses_wmg(*s->g)) {
+        gw.push_back(s->g);
+        wa.push_back(wmg_of(*s));
+      }
     }
     prepare_init_batch(t_init_, gs, ia, st_);
     launch_init_batch(t_init_, st_);
     prepare_backward_batch(t_ib_, gs, ba, st_);
-    launch_backward_batch(t_ib_, BWD_CGLS, st_);
-    prepare_wmg_batch(t_iw_, gs, wa, st_);
+    launch_backward_batch(t_ib_, BWD_CGLS_INIT, st_);
+    prepare_wmg_batch(t_iw_, gw, wa, st_);
     launch_wmg_batch(t_iw_, WMG_CGLS_INIT, st_);
     for (Slot* s : slots) active_.push_back(s);
     dirty_ = true;
@@ -218,9 +221,15 @@ class Engine {
   static BwdArgs bwd_of(const Slot& s) {
     BwdArgs a{};
     a.sino = s.w->r;
+    a.q = s.w->q;
     a.out = s.w->s;
     a.x = s.x;
+    a.p = s.w->p;
+    a.zP = s.w->zP;
+    a.zTP = s.w->zTP;
+    a.identity = s.o.precond == RECO_PRECOND_NONE;
     a.st = s.w->st;
+    a.red = red_of(*s.w, 1);
     return a;
   }
   static WmgArgs wmg_of(const Slot& s) {
@@ -236,20 +245,19 @@ class Engine {
     return a;
   }
 
-  // One CGLS iteration of every running problem (the solo iteration's four
-  // launches, each over the shared work list).
+  // One CGLS iteration of every running problem (the solo iteration's
+  // launches, each over the shared work list; the WMG list holds only the
+  // problems whose preconditioner is not applied inside the backprojection).
   void iteration(hipStream_t s) {
     launch_forward_batch(t_fwd_, FWD_CGLS, s);
-    launch_update_batch(t_upd_, s);
     launch_backward_batch(t_bwd_, BWD_CGLS, s);
     launch_wmg_batch(t_wmg_, WMG_CGLS, s);
   }
 
   void rebuild() {
     drop_graph();
-    std::vector<const Geometry*> gs;
+    std::vector<const Geometry*> gs, gw;
     std::vector<FwdArgs> fa;
-    std::vector<UpdArgs> ua;
     std::vector<BwdArgs> ba;
     std::vector<WmgArgs> wa;
     std::vector<SolverState*> sts;
@@ -260,25 +268,20 @@ class Engine {
       f.imgP = w.zP;
       f.imgTP = w.zTP;
       f.out = w.q;
+      f.r = w.r;
       f.st = w.st;
       f.red = red_of(w, 0);
       fa.push_back(f);
-      UpdArgs u{};
-      u.x = s->x;
-      u.p = w.p;
-      u.r = w.r;
-      u.zP = w.zP;
-      u.q = w.q;
-      u.st = w.st;
-      ua.push_back(u);
       ba.push_back(bwd_of(*s));
-      wa.push_back(wmg_of(*s));
+      if (!backward_fuses_wmg(*s->g)) {
+        gw.push_back(s->g);
+        wa.push_back(wmg_of(*s));
+      }
       sts.push_back(w.st);
     }
     prepare_forward_batch(t_fwd_, gs, fa, st_);
-    prepare_update_batch(t_upd_, gs, ua, st_);
     prepare_backward_batch(t_bwd_, gs, ba, st_);
-    prepare_wmg_batch(t_wmg_, gs, wa, st_);
+    prepare_wmg_batch(t_wmg_, gw, wa, st_);
     const int cnt = (int)sts.size();
     if (cnt > flag_cap_) {
       if (d_sts_) (void)hipFree(d_sts_);
@@ -334,7 +337,7 @@ class Engine {
   bool dirty_ = true;
   int clean_ticks_ = 0;
   hipGraphExec_t exec_ = nullptr;
-  DevTable t_fwd_, t_upd_, t_bwd_, t_wmg_;   // iteration work lists
+  DevTable t_fwd_, t_bwd_, t_wmg_;           // iteration work lists
   DevTable t_init_, t_ib_, t_iw_;            // initialisation of new problems
   SolverState** d_sts_ = nullptr;
   Flag* d_flags_ = nullptr;

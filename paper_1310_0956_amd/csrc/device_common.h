@@ -62,6 +62,13 @@ __device__ __forceinline__ void block_sum256(double (&v)[W], double* sh) {
 // Each block contributes W partial sums; the last block to arrive sums them in
 // block order and calls fin(totals) from thread 0.  Returns nothing; the
 // counter is reset for the next use.  Blocks have NW waves.
+//
+// Visibility without a full L2 writeback: the partials are written with
+// agent-scope atomic stores, which write through to the device-coherent
+// level, and the block waits for their completion (vmcnt) before taking its
+// ticket; the last block reads them with agent-scope atomic loads.  Results
+// the finisher writes to the solver state are read by later launches (kernel
+// boundaries order them).
 template <int W, int NW = 4, typename F>
 __device__ __forceinline__ void reduce_and_finish(double (&v)[W], const RedScratch& red,
                                                   int nblocks, int block_id, F fin) {
@@ -70,14 +77,16 @@ __device__ __forceinline__ void reduce_and_finish(double (&v)[W], const RedScrat
   block_sum<W, NW>(v, sh);
   if (threadIdx.x == 0) {
 #pragma unroll
-    for (int i = 0; i < W; ++i) red.partial[(size_t)block_id * W + i] = v[i];
-    __threadfence();
-    const unsigned t = atomicAdd(red.counter, 1u);
+    for (int i = 0; i < W; ++i)
+      __hip_atomic_store(&red.partial[(size_t)block_id * W + i], v[i], __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_AGENT);
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    const unsigned t =
+        __hip_atomic_fetch_add(red.counter, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     am_last = (t == (unsigned)nblocks - 1u);
   }
   __syncthreads();
   if (!am_last) return;
-  __threadfence();
   double acc[W];
 #pragma unroll
   for (int i = 0; i < W; ++i) acc[i] = 0.0;
@@ -90,12 +99,47 @@ __device__ __forceinline__ void reduce_and_finish(double (&v)[W], const RedScrat
   block_sum<W, NW>(acc, sh);
   if (threadIdx.x == 0) {
     fin(acc);
-    *red.counter = 0u;
-    __threadfence();
+    __hip_atomic_store(red.counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
 }
 
 __device__ __forceinline__ bool finite(double v) { return __builtin_isfinite(v); }
+
+// End of the preconditioning step of a CGLS iteration, run once by the last
+// block from the totals t = {<s,z>, ||s||^2, ||z||^2, <z,p>} (p = the current
+// direction; only used with lambda > 0).  init: the step before the first
+// iteration (z_0 = M^-1 s_0, gamma_0 = <s_0,z_0>, reference norm ||s_0||).
+// Otherwise: beta = gamma'/gamma, the squared norm of the next direction
+// z + beta p, the relative residual ||s|| / ||s_0|| and the stopping test.
+__device__ __forceinline__ void cgls_precond_finish(SolverState* st, const double (&t)[4],
+                                                    bool init) {
+  if (init) {
+    st->gamma = t[0];
+    st->s0 = sqrt(t[1]);
+    st->beta = 0.0;
+    st->pp = t[2];
+    st->relres = 1.0;
+    st->iter = 0;
+    st->init = 1;
+    if (!finite(st->s0) || !finite(t[0])) st->done = 3;
+    else if (st->s0 == 0.0) { st->done = 1; st->relres = 0.0; }
+    return;
+  }
+  const double g = t[0];
+  const double beta = g / st->gamma;
+  st->pp = t[2] + 2.0 * beta * t[3] + beta * beta * st->pp;
+  st->beta = beta;
+  st->gamma = g;
+  st->iter += 1;
+  const double rr = sqrt(t[1]) / st->s0;
+  st->relres = rr;
+  if (st->hist && st->iter <= st->hist_cap) st->hist[st->iter - 1] = rr;
+  if (!finite(rr) || !finite(beta)) st->done = 3;
+  else if (st->fixed) { if (st->iter >= st->max_iter) st->done = 1; }
+  else if (rr <= st->tol) st->done = 1;
+  else if (st->iter >= st->max_iter) st->done = 2;
+  else if (g == 0.0) st->done = 1;
+}
 
 // Position of a block within its problem's grid.
 struct BlockPos {

@@ -165,12 +165,13 @@ struct DevTable {
 // Kernel launchers (project.hip, backproject.hip, wmg.hip, vec.hip)
 // ---------------------------------------------------------------------------
 enum FwdMode { FWD_PLAIN = 0, FWD_CGLS = 1, FWD_SIRT = 2, FWD_COUNT = 3 };
-enum BwdMode { BWD_PLAIN = 0, BWD_CGLS = 1, BWD_SIRT = 2, BWD_AXPY = 3 };
+enum BwdMode { BWD_PLAIN = 0, BWD_CGLS = 1, BWD_SIRT = 2, BWD_AXPY = 3, BWD_CGLS_INIT = 4 };
 
 struct FwdArgs {
   const void* imgP;    // [n][ld] padded image
   const void* imgTP;   // [n][ld] padded transposed image
   void* out;           // [m][nb]
+  void* r;             // CGLS: residual [m][nb] (r -= alpha q_old before q is replaced)
   const void* b;       // SIRT: measured data
   const void* R;       // SIRT: inverse row sums
   SolverState* st;     // CGLS/SIRT: state (may be null)
@@ -179,16 +180,26 @@ struct FwdArgs {
 };
 
 struct BwdArgs {
-  const void* sino;    // [m][nb]
-  void* out;           // [n][n]
-  const void* x;       // extra-term source (CGLS: current x; AXPY: xin)
+  const void* sino;    // [m][nb] (CGLS: the residual before this iteration's step)
+  void* out;           // [n][n] (CGLS: s, written only when the WMG apply is separate)
+  const void* x;       // extra-term source (CGLS: current x, updated; AXPY: xin)
   const void* f;       // AXPY: right-hand side term
   const void* C;       // SIRT: inverse column sums
   SolverState* st;
   RedScratch red;
   int x_ld = 0, x_off = 0;       // AXPY: layout of x
   double sa = 1.0, sx = 0.0, sf = 0.0;  // AXPY: out = sa*W^T r + sx*x + sf*f
+  // CGLS: the step uses r - alpha q; p = z + beta p and x += alpha p are
+  // applied to the tile's pixels, and for 2^L <= 16 the WMG apply of the new
+  // s is done in the same launch, writing z to zP / zTP.
+  const void* q = nullptr;       // [m][nb] projected direction
+  void* p = nullptr;             // [n][n] direction
+  void* zP = nullptr;            // padded z (read: previous z; written: new z)
+  void* zTP = nullptr;           // padded transposed z (written)
+  bool identity = false;         // no preconditioner: z = s
 };
+// True when the CGLS backprojection also applies the WMG preconditioner.
+bool backward_fuses_wmg(const Geometry& g);
 
 void launch_pad_transpose(const Geometry& g, const void* x, void* xP, void* xTP,
                           hipStream_t st);
@@ -217,8 +228,6 @@ void compute_packet_diagonal(Geometry& g, hipStream_t st);
 // vector kernels (vec.hip)
 void launch_fill(void* p, size_t count, bool f64, double value, hipStream_t st);
 void launch_copy(const void* src, void* dst, size_t count, bool f64, hipStream_t st);
-void launch_cgls_update(const Geometry& g, void* x, void* p, const void* zP, void* r,
-                        const void* q, SolverState* st, hipStream_t s);
 void launch_invert(void* v, size_t count, bool f64, hipStream_t st);
 void launch_state_init(SolverState* st, double tol, int max_iter, int fixed, double lambda,
                        double* hist, int hist_cap, hipStream_t s);
@@ -234,14 +243,6 @@ void launch_backward_batch(const DevTable& t, BwdMode mode, hipStream_t st);
 void prepare_wmg_batch(DevTable& t, const std::vector<const Geometry*>& gs,
                        const std::vector<WmgArgs>& as, hipStream_t st);
 void launch_wmg_batch(const DevTable& t, WmgMode mode, hipStream_t st);
-struct UpdArgs {
-  void *x, *p, *r;
-  const void *zP, *q;
-  SolverState* st;
-};
-void prepare_update_batch(DevTable& t, const std::vector<const Geometry*>& gs,
-                          const std::vector<UpdArgs>& as, hipStream_t st);
-void launch_update_batch(const DevTable& t, hipStream_t st);
 struct InitArgs {
   void *x, *p, *q, *r;
   const void* b;

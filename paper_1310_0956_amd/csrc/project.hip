@@ -32,9 +32,14 @@ namespace {
 
 constexpr int kSlots = 8;       // angles per block
 constexpr int kBins = 32;       // bins per block
-constexpr int kWinCols = 128;   // staged columns per band
+constexpr int kStride = 126;    // LDS row stride of a staged band (elements); two
+                                // float bands plus the block's other shared data
+                                // stay under 32 KB, so five blocks fit in a CU
+constexpr int kWinCols = 122;   // widest window staged in LDS; columns past the
+                                // window's width read zeros (guard columns)
 constexpr int kThreads = kSlots * kBins;
-constexpr int kStageRows = kThreads / kWinCols;   // rows loaded per staging pass
+constexpr int kLoadCols = 128;                    // staging: threads per row
+constexpr int kStageRows = kThreads / kLoadCols;  // rows loaded per staging pass
 
 template <typename T>
 constexpr int kBand = sizeof(T) == 4 ? 32 : 16;   // rows per staged band
@@ -44,6 +49,7 @@ struct FwdK {
   const T* imgP;
   const T* imgTP;
   T* out;
+  T* r;                // CGLS: residual, updated with the previous step
   const T* b;
   const T* R;
   const FwdAngle* ang;
@@ -137,34 +143,57 @@ __device__ __forceinline__ T wM(const FwdAngle& a) {
   if constexpr (sizeof(T) == 4) return a.Wmaxf; else return a.Wmax;
 }
 
-// `rows` rows of one ray read from an LDS window (row stride kWinCols).  The
-// window-relative column is clamped into [lo_w, hi_w]: the window images of
-// image columns -2 and n, intersected with the loaded part of the window.
-template <typename T>
-__device__ __forceinline__ void band_lds(const T* __restrict__ w, Walk<T>& wk, int rows, int lo_w,
-                                         int hi_w, T B, T C, T Wm, T& acc0, T& acc1) {
+// `rows` rows of one ray read from an LDS window (row stride kStride).
+// Float path: the walker's column is relative to the window start and is
+// clamped as an unsigned value to `width`, so a ray left or right of the
+// window (only rays outside the image can be) reads the zero guard columns
+// width and width + 1; rays inside the image stay in [0, width - 2].  The left
+// weight is clamp(lo * Bq + Cq, 0, Wm) with lo the 32-bit fraction of the
+// position, Bq = -B 2^-32 and Cq = C + B/2 (the trapezoid (1/2 - f) B + C).
+__device__ __forceinline__ void band_lds(const float* __restrict__ w, Walk<float>& wk, int rows,
+                                         unsigned width, float Bq, float Cq, float Wm,
+                                         float& acc0, float& acc1) {
+  unsigned long long p = wk.p;
+  const unsigned long long dp = wk.dp;
   int r = 0;
   for (; r + 3 < rows; r += 4) {
-    T w0[4], x0[4], x1[4];
+    float w0[4], x0[4], x1[4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-      const int c = iclamp(wk.col(), lo_w, hi_w);
-      const T* q = w + (r + u) * kWinCols + c;
+      const unsigned c = min((unsigned)(p >> 32), width);
+      const float* q = w + (r + u) * kStride + c;
       x0[u] = q[0];
       x1[u] = q[1];
-      w0[u] = left_weight(wk.frac(), B, C, Wm);
-      wk.step();
+      w0[u] = __builtin_amdgcn_fmed3f(fmaf((float)(unsigned)p, Bq, Cq), 0.0f, Wm);
+      p += dp;
+      asm volatile("" : "+v"(p));   // one position register: keep LLVM from cloning it per row
     }
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-      acc0 = fma(w0[u], x0[u] - x1[u], acc0);
+      acc0 = fmaf(w0[u], x0[u] - x1[u], acc0);
       acc1 += x1[u];
     }
   }
   for (; r < rows; ++r) {
+    const unsigned c = min((unsigned)(p >> 32), width);
+    const float* q = w + r * kStride + c;
+    const float x0 = q[0], x1 = q[1];
+    acc0 = fmaf(__builtin_amdgcn_fmed3f(fmaf((float)(unsigned)p, Bq, Cq), 0.0f, Wm), x0 - x1, acc0);
+    acc1 += x1;
+    p += dp;
+  }
+  wk.p = p;
+}
+
+// Double path: the window-relative column is clamped into [lo_w, hi_w], the
+// window images of image columns -2 and n.
+__device__ __forceinline__ void band_lds(const double* __restrict__ w, Walk<double>& wk, int rows,
+                                         int lo_w, int hi_w, double B, double C, double Wm,
+                                         double& acc0, double& acc1) {
+  for (int r = 0; r < rows; ++r) {
     const int c = iclamp(wk.col(), lo_w, hi_w);
-    const T* q = w + r * kWinCols + c;
-    const T x0 = q[0], x1 = q[1];
+    const double* q = w + r * kStride + c;
+    const double x0 = q[0], x1 = q[1];
     acc0 = fma(left_weight(wk.frac(), B, C, Wm), x0 - x1, acc0);
     acc1 += x1;
     wk.step();
@@ -217,7 +246,9 @@ __device__ __forceinline__ void forward_body(const FwdK<T>& a, const BlockPos bp
   constexpr int BAND = kBand<T>;
   constexpr int STAGE_PER = BAND / kStageRows;   // loads per thread per band
   if (a.st && a.st->done) return;   // solver finished: later launches are no-ops
-  __shared__ T win[2][BAND * kWinCols];
+  double alpha_prev = 0.0;
+  if constexpr (MODE == FWD_CGLS) alpha_prev = a.st->alpha;
+  __shared__ T win[2][BAND * kStride];
   __shared__ int sh_lo[kThreads / 64], sh_hi[kThreads / 64];
   const int t = threadIdx.x;
   const int lane = t & 63, wv = t >> 6;
@@ -272,13 +303,17 @@ __device__ __forceinline__ void forward_body(const FwdK<T>& a, const BlockPos bp
   const bool cfirst = (cc & 1) == 0;
 
   const T B = wB<T>(ang), C = wC<T>(ang), Wm = wM<T>(ang);
+  const float Bq = (float)(-ang.B * 2.3283064365386963e-10), Cq = (float)(ang.C + 0.5 * ang.B);
   T acc0 = T(0), acc1 = T(0);
   const int nbands = hi >= lo ? (hi - lo + BAND) / BAND : 0;
   Walk<T> wk;
   wk.init(fma((double)lo, ang.slope, P0), ang.slope, ang.dP);
-  // staging: thread loads column (t % kWinCols) of rows (t / kWinCols) + kStageRows * i
-  const int scol = t % kWinCols;
-  const int srow = __builtin_amdgcn_readfirstlane(t / kWinCols);   // uniform per wave
+  // staging: thread loads column (t % kLoadCols) of rows (t / kLoadCols) + kStageRows * i;
+  // columns past the window's width are written as zeros (the guard columns);
+  // threads with scol >= kStride only idle
+  const int scol = t % kLoadCols;
+  const bool stager = scol < kStride;
+  const int srow = __builtin_amdgcn_readfirstlane(t / kLoadCols);   // uniform per wave
   const int rbytes = a.ld * (int)sizeof(T);
   Window wcur{0, 0};
   int cur_shift = 0;   // window start the walker's columns are currently relative to
@@ -291,7 +326,7 @@ __device__ __forceinline__ void forward_body(const FwdK<T>& a, const BlockPos bp
         T v = T(0);
         if (scol <= wcur.c1 - wcur.c0)
           v = load_elem(rs, (unsigned)(wcur.c0 + kPad + scol) * sizeof(T), (lo + row) * rbytes, T(0));
-        win[0][row * kWinCols + scol] = v;
+        if (stager) win[0][row * kStride + scol] = v;
       }
     }
     __syncthreads();
@@ -324,14 +359,18 @@ __device__ __forceinline__ void forward_body(const FwdK<T>& a, const BlockPos bp
     cur_shift = wcur.c0;
     const int width = wcur.c1 - wcur.c0 + 1;
     if (width <= kWinCols) {
-      band_lds<T>(win[cur], wk, rows, max(-2 - wcur.c0, 0), min(n - wcur.c0, width - 2), B, C, Wm,
-                  acc0, acc1);
+      if constexpr (sizeof(T) == 4)
+        band_lds(win[cur], wk, rows, (unsigned)width, Bq, Cq, Wm, acc0, acc1);
+      else
+        band_lds(win[cur], wk, rows, max(-2 - wcur.c0, 0), min(n - wcur.c0, width - 2), B, C, Wm,
+                 acc0, acc1);
     } else {
       band_mem<T>(rs, a.ld, n, rb, rows, wcur.c0, wk, B, C, Wm, acc0, acc1);
     }
     if (next_lds) {
 #pragma unroll
-      for (int i = 0; i < STAGE_PER; ++i) win[nxt][(srow + kStageRows * i) * kWinCols + scol] = pre[i];
+      for (int i = 0; i < STAGE_PER; ++i)
+        if (stager) win[nxt][(srow + kStageRows * i) * kStride + scol] = pre[i];
     }
     wcur = wnext;
     __syncthreads();
@@ -343,10 +382,15 @@ __device__ __forceinline__ void forward_body(const FwdK<T>& a, const BlockPos bp
   } else if constexpr (MODE == FWD_SIRT) {
     if (valid) a.out[i] = (T)((double)a.R[i] * ((double)a.b[i] - (double)result));
   } else if constexpr (MODE == FWD_CGLS) {
+    // The residual update of the previous iteration, r -= alpha q_old (alpha
+    // of that iteration: this launch's last block overwrites it only after
+    // every block has read it), then
     // q = W z + beta q_old  (q_old = W p_old, so q = W (z + beta p_old) = W p_new)
     double q = 0.0;
     if (valid) {
-      q = (double)result + a.st->beta * (double)a.out[i];
+      const double q_old = (double)a.out[i];
+      a.r[i] = (T)((double)a.r[i] - alpha_prev * q_old);
+      q = (double)result + a.st->beta * q_old;
       a.out[i] = (T)q;
       q = (double)(T)q;
     }
@@ -454,6 +498,7 @@ FwdK<T> make_args(const Geometry& g, const FwdArgs& a) {
   k.imgP = (const T*)a.imgP;
   k.imgTP = (const T*)a.imgTP;
   k.out = (T*)a.out;
+  k.r = (T*)a.r;
   k.b = (const T*)a.b;
   k.R = (const T*)a.R;
   k.ang = g.d_fwd;

@@ -188,26 +188,40 @@ static void drive(Workspace& w, const reco_solve_opts& o, int limit, hipStream_t
 // ---------------------------------------------------------------------------
 // CGLS
 // ---------------------------------------------------------------------------
-// One iteration (4 launches):
-//   K1: q = W z + beta q   (= W p_new),  delta = ||q||^2 + lambda ||p_new||^2,  alpha
-//   K7: p = z + beta p;  x += alpha p;  r -= alpha q
-//   K2: s = W^T r - lambda x
-//   K4: z = M^-1 s;  gamma' = <s,z>, beta = gamma'/gamma, relres = ||s||/||s_0||
-void cgls_iteration(Geometry& g, Workspace& w, void* x, const reco_solve_opts& o, hipStream_t st) {
+// One iteration (2 launches; 3 when 2^L > 16):
+//   K1 forward:  r -= alpha_prev q (the previous step, deferred);
+//                q = W z + beta q (= W p_new);  delta = ||q||^2 + lambda ||p_new||^2;
+//                alpha = gamma / delta
+//   K2 backward: p = z + beta p;  x += alpha p;  s = W^T (r - alpha q) - lambda x;
+//                z = M^-1 s (in the same launch when 2^L <= 16, else K4);
+//                gamma' = <s,z>, beta = gamma'/gamma, relres = ||s||/||s_0||, stop test
+static FwdArgs cgls_fwd_args(Workspace& w) {
   FwdArgs fa{};
   fa.imgP = w.zP;
   fa.imgTP = w.zTP;
   fa.out = w.q;
+  fa.r = w.r;
   fa.st = w.st;
   fa.red = red_of(w, 0);
-  launch_forward(g, FWD_CGLS, fa, st);
-  launch_cgls_update(g, x, w.p, w.zP, w.r, w.q, w.st, st);
+  return fa;
+}
+
+static BwdArgs cgls_bwd_args(Workspace& w, void* x, const reco_solve_opts& o) {
   BwdArgs ba{};
   ba.sino = w.r;
+  ba.q = w.q;
   ba.out = w.s;
   ba.x = x;
+  ba.p = w.p;
+  ba.zP = w.zP;
+  ba.zTP = w.zTP;
+  ba.identity = o.precond == RECO_PRECOND_NONE;
   ba.st = w.st;
-  launch_backward(g, BWD_CGLS, ba, st);
+  ba.red = red_of(w, 1);
+  return ba;
+}
+
+static WmgArgs cgls_wmg_args(Workspace& w, const reco_solve_opts& o) {
   WmgArgs wa{};
   wa.s = w.s;
   wa.zP = w.zP;
@@ -217,9 +231,16 @@ void cgls_iteration(Geometry& g, Workspace& w, void* x, const reco_solve_opts& o
   wa.identity = o.precond == RECO_PRECOND_NONE;
   wa.st = w.st;
   wa.red = red_of(w, 1);
-  launch_wmg(g, WMG_CGLS, wa, st);
+  return wa;
 }
 
+void cgls_iteration(Geometry& g, Workspace& w, void* x, const reco_solve_opts& o, hipStream_t st) {
+  launch_forward(g, FWD_CGLS, cgls_fwd_args(w), st);
+  launch_backward(g, BWD_CGLS, cgls_bwd_args(w, x, o), st);
+  if (!backward_fuses_wmg(g)) launch_wmg(g, WMG_CGLS, cgls_wmg_args(w, o), st);
+}
+
+// x = p = q = 0, r = b, then s_0 = W^T b - lambda x, z_0 = M^-1 s_0.
 void cgls_setup(Geometry& g, Workspace& w, const void* b, void* x, const reco_solve_opts& o,
                 hipStream_t st) {
   const bool fixed = o.fixed_iters > 0;
@@ -230,22 +251,8 @@ void cgls_setup(Geometry& g, Workspace& w, const void* b, void* x, const reco_so
   launch_fill(w.p, g.N(), g.f64, 0.0, st);
   launch_fill(w.q, g.M(), g.f64, 0.0, st);
   launch_copy(b, w.r, g.M(), g.f64, st);
-  BwdArgs ba{};
-  ba.sino = w.r;
-  ba.out = w.s;
-  ba.x = x;
-  ba.st = w.st;
-  launch_backward(g, BWD_CGLS, ba, st);
-  WmgArgs wa{};
-  wa.s = w.s;
-  wa.zP = w.zP;
-  wa.zTP = w.zTP;
-  wa.pold = w.p;
-  wa.lambda = o.lambda;
-  wa.identity = o.precond == RECO_PRECOND_NONE;
-  wa.st = w.st;
-  wa.red = red_of(w, 1);
-  launch_wmg(g, WMG_CGLS_INIT, wa, st);
+  launch_backward(g, BWD_CGLS_INIT, cgls_bwd_args(w, x, o), st);
+  if (!backward_fuses_wmg(g)) launch_wmg(g, WMG_CGLS_INIT, cgls_wmg_args(w, o), st);
 }
 
 reco_status solve_cgls(Geometry& g, const void* b, void* x, const reco_solve_opts& o,

@@ -1,6 +1,5 @@
 // Streaming vector kernels of the Krylov solvers (HBM bound): fills, copies,
-// the fused CGLS update, reciprocal with 1/0 := 0, state initialisation.
-// Update arithmetic is done in float64 and rounded to the storage type.
+// reciprocal with 1/0 := 0, state initialisation (also for a whole batch).
 #include "device_common.h"
 #include "timing.h"
 
@@ -29,60 +28,6 @@ __global__ void k_invert(T* p, size_t count) {
     const T v = p[i];
     p[i] = v != T(0) ? T(1) / v : T(0);
   }
-}
-
-// p = z + beta p; x += alpha p   (pixels, blocks [0, nbN))
-// r -= alpha q                   (rays,   blocks [nbN, ...))
-template <typename T>
-struct UpdK {
-  T* x;
-  T* p;
-  const T* zP;
-  T* r;
-  const T* q;
-  const SolverState* st;
-  int n, ld, nbN;
-  size_t M;
-};
-
-template <typename T>
-__device__ __forceinline__ void update_body(const UpdK<T>& a, int b) {
-  const SolverState* st = a.st;
-  if (st->done) return;
-  const double alpha = st->alpha, beta = st->beta;
-  T* __restrict__ x = a.x;
-  T* __restrict__ p = a.p;
-  T* __restrict__ r = a.r;
-  const T* __restrict__ zP = a.zP;
-  const T* __restrict__ q = a.q;
-  const int n = a.n, ld = a.ld, nbN = a.nbN;
-  const size_t M = a.M;
-  if (b < nbN) {
-    const size_t N = (size_t)n * n;
-    const size_t i = (size_t)b * 256 + threadIdx.x;
-    if (i < N) {
-      const size_t iy = i / n, ix = i % n;
-      const double z = (double)zP[iy * ld + ix + kPad];
-      const T pn = (T)(z + beta * (double)p[i]);
-      p[i] = pn;
-      x[i] = (T)((double)x[i] + alpha * (double)pn);
-    }
-  } else {
-    const size_t i = (size_t)(b - nbN) * 256 + threadIdx.x;
-    if (i < M) r[i] = (T)((double)r[i] - alpha * (double)q[i]);
-  }
-}
-
-template <typename T>
-__global__ __launch_bounds__(256) void k_cgls_update(UpdK<T> a) {
-  update_body<T>(a, blockIdx.x);
-}
-
-__global__ __launch_bounds__(256) void k_update_batch(const UpdK<float>* __restrict__ args,
-                                                      const int* __restrict__ start,
-                                                      const int* __restrict__ gx, int count) {
-  const int r = batch_find(start, count, blockIdx.x);
-  update_body<float>(args[r], (int)blockIdx.x - start[r]);
 }
 
 // Start of a CGLS solve for one problem of a batch: state, x = p = q = 0, r = b.
@@ -141,27 +86,6 @@ unsigned grid_for(size_t count) {
   return (unsigned)(b > 65536 ? 65536 : (b == 0 ? 1 : b));
 }
 
-template <typename T>
-UpdK<T> upd_args(const Geometry& g, void* x, void* p, const void* zP, void* r, const void* q,
-                 const SolverState* st) {
-  UpdK<T> k;
-  k.x = (T*)x;
-  k.p = (T*)p;
-  k.zP = (const T*)zP;
-  k.r = (T*)r;
-  k.q = (const T*)q;
-  k.st = st;
-  k.n = g.n;
-  k.ld = g.ld;
-  k.nbN = (int)((g.N() + 255) / 256);
-  k.M = g.M();
-  return k;
-}
-
-int update_blocks(const Geometry& g) {
-  return (int)((g.N() + 255) / 256) + (int)((g.M() + 255) / 256);
-}
-
 }  // namespace
 
 void launch_fill(void* p, size_t count, bool f64, double value, hipStream_t st) {
@@ -182,38 +106,6 @@ void launch_invert(void* v, size_t count, bool f64, hipStream_t st) {
   if (count == 0) return;
   if (f64) hipLaunchKernelGGL(k_invert<double>, dim3(grid_for(count)), dim3(256), 0, st, (double*)v, count);
   else hipLaunchKernelGGL(k_invert<float>, dim3(grid_for(count)), dim3(256), 0, st, (float*)v, count);
-  HIP_CHECK(hipGetLastError());
-}
-
-void launch_cgls_update(const Geometry& g, void* x, void* p, const void* zP, void* r, const void* q,
-                        SolverState* st, hipStream_t s) {
-  TimedLaunch tl(TK_UPDATE, s);
-  if (g.f64)
-    hipLaunchKernelGGL(k_cgls_update<double>, dim3(update_blocks(g)), dim3(256), 0, s,
-                       upd_args<double>(g, x, p, zP, r, q, st));
-  else
-    hipLaunchKernelGGL(k_cgls_update<float>, dim3(update_blocks(g)), dim3(256), 0, s,
-                       upd_args<float>(g, x, p, zP, r, q, st));
-  HIP_CHECK(hipGetLastError());
-}
-
-void prepare_update_batch(DevTable& t, const std::vector<const Geometry*>& gs,
-                          const std::vector<UpdArgs>& as, hipStream_t st) {
-  std::vector<UpdK<float>> host(gs.size());
-  std::vector<int> blocks(gs.size()), widths(gs.size());
-  for (size_t i = 0; i < gs.size(); ++i) {
-    host[i] = upd_args<float>(*gs[i], as[i].x, as[i].p, as[i].zP, as[i].r, as[i].q, as[i].st);
-    blocks[i] = update_blocks(*gs[i]);
-    widths[i] = blocks[i];
-  }
-  t.upload(host.data(), sizeof(UpdK<float>), blocks, widths, st);
-}
-
-void launch_update_batch(const DevTable& t, hipStream_t st) {
-  if (t.count == 0) return;
-  TimedLaunch tl(TK_UPDATE, st);
-  hipLaunchKernelGGL(k_update_batch, dim3(t.total_blocks), dim3(256), 0, st,
-                     (const UpdK<float>*)t.args, t.start, t.gx, t.count);
   HIP_CHECK(hipGetLastError());
 }
 

@@ -135,35 +135,9 @@ __device__ __forceinline__ void wmg_body(const WmgK<T>& a, const BlockPos bp) {
         v[3] += z * (double)a.pold[(size_t)iy * n + ix];
     }
     SolverState* st = a.st;
-    reduce_and_finish<4>(v, a.red, bp.count(), bp.id(),
-                         [st](double (&t)[4]) {
-                           if (MODE == WMG_CGLS_INIT) {
-                             st->gamma = t[0];
-                             st->s0 = sqrt(t[1]);
-                             st->beta = 0.0;
-                             st->pp = t[2];
-                             st->relres = 1.0;
-                             st->iter = 0;
-                             st->init = 1;
-                             if (!finite(st->s0) || !finite(t[0])) st->done = 3;
-                             else if (st->s0 == 0.0) { st->done = 1; st->relres = 0.0; }
-                           } else {
-                             const double g = t[0];
-                             const double beta = g / st->gamma;
-                             st->pp = t[2] + 2.0 * beta * t[3] + beta * beta * st->pp;
-                             st->beta = beta;
-                             st->gamma = g;
-                             st->iter += 1;
-                             const double rr = sqrt(t[1]) / st->s0;
-                             st->relres = rr;
-                             if (st->hist && st->iter <= st->hist_cap) st->hist[st->iter - 1] = rr;
-                             if (!finite(rr) || !finite(beta)) st->done = 3;
-                             else if (st->fixed) { if (st->iter >= st->max_iter) st->done = 1; }
-                             else if (rr <= st->tol) st->done = 1;
-                             else if (st->iter >= st->max_iter) st->done = 2;
-                             else if (g == 0.0) st->done = 1;
-                           }
-                         });
+    reduce_and_finish<4>(v, a.red, bp.count(), bp.id(), [st](double (&t)[4]) {
+      cgls_precond_finish(st, t, MODE == WMG_CGLS_INIT);
+    });
   }
 }
 
