@@ -13,7 +13,8 @@
 // so a ray outside the image reads zeros.
 //
 // Work decomposition: a block takes up to 8 neighbouring angles that share the
-// walk axis ("group") times 32 neighbouring detector bins, one ray per thread.
+// walk axis ("group") times 32 neighbouring detector bins, one ray per thread
+// (each wave: two angles, interleaved across its lanes).
 // It walks the rows in bands: the columns the block's rays cross in a band
 // (known from the corner rays, since positions are linear in bin and row) are
 // staged in LDS with coalesced loads, double buffered through registers, and
@@ -257,8 +258,11 @@ __device__ __forceinline__ void forward_body(const FwdK<T>& a, const BlockPos bp
   const int jfirst = bp.x * kBins;
   const int jlast = min(jfirst + kBins - 1, nb - 1);
   const int k0 = a.groups[g * kSlots];            // first angle: sets the walk axis
-  const int kl = a.groups[g * kSlots + (t >> 5)];
-  const int jown = jfirst + (t & 31);
+  // ray of this thread: a wave holds two angles of the group, interleaved by
+  // lane parity, so that each half-wave's LDS reads span about 16 bins' worth
+  // of columns (fewer bank conflicts than 32 bins of one angle)
+  const int kl = a.groups[g * kSlots + ((t >> 6) << 1) + (t & 1)];
+  const int jown = jfirst + ((t >> 1) & 31);
   const bool valid = kl >= 0 && jown <= jlast;
   // invalid lanes shadow the block's first ray so that they stay in the window
   const int k = valid ? kl : k0;
