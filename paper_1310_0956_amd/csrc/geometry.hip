@@ -79,6 +79,8 @@ Geometry::~Geometry() {
   auto f = [](void* p) { if (p) (void)hipFree(p); };
   f(d_fwd);
   f(d_groups);
+  f(d_fwd_rows);
+  f(d_fwd_wins);
   f(d_bwd);
   f(d_diag64);
   f(d_diag);
@@ -133,6 +135,7 @@ Geometry* create_geometry(const reco_geometry_desc& d, hipStream_t st) {
                            hipMemcpyHostToDevice, st));
   HIP_CHECK(hipMemcpyAsync(g->d_bwd, g->h_bwd.data(), sizeof(BwdAngle) * g->m,
                            hipMemcpyHostToDevice, st));
+  build_forward_windows(*g, st);
   HIP_CHECK(hipMalloc(&g->d_diag64, sizeof(double) * g->N()));
   HIP_CHECK(hipMalloc(&g->d_diag, g->esize() * g->N()));
   compute_packet_diagonal(*g, st);

@@ -83,6 +83,9 @@ struct Geometry {
   FwdAngle* d_fwd = nullptr;   // [m]
   int* d_groups = nullptr;     // [ngroups][8] angle groups walked together (forward)
   int ngroups = 0;
+  void* d_fwd_rows = nullptr;  // [ngroups * bin blocks] row range of each forward block
+  void* d_fwd_wins = nullptr;  // [ngroups * bin blocks][fwd_maxb] band column windows
+  int fwd_maxb = 0;
   BwdAngle* d_bwd = nullptr;   // [m]
   std::vector<FwdAngle> h_fwd;
   std::vector<BwdAngle> h_bwd;
@@ -201,6 +204,7 @@ struct BwdArgs {
 // True when the CGLS backprojection also applies the WMG preconditioner.
 bool backward_fuses_wmg(const Geometry& g);
 
+void build_forward_windows(Geometry& g, hipStream_t st);
 void launch_pad_transpose(const Geometry& g, const void* x, void* xP, void* xTP,
                           hipStream_t st);
 void launch_forward(const Geometry& g, FwdMode mode, const FwdArgs& a, hipStream_t st);

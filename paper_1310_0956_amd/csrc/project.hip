@@ -55,6 +55,9 @@ struct FwdK {
   const T* R;
   const FwdAngle* ang;
   const int* groups;   // [ngroups][8] angle indices, -1 = empty slot
+  const int2* rows;    // [ngroups * nbx] row range of each block
+  const int2* wins;    // [ngroups * nbx][maxb] column window of each band
+  int nbx, maxb;
   SolverState* st;
   RedScratch red;
   unsigned long long* count;
@@ -217,29 +220,88 @@ __device__ __forceinline__ void band_mem(__amdgpu_buffer_rsrc_t rs, int ld, int 
   }
 }
 
-// Column window [c0, c1] of band rows [rb, re]: the floor(P) range over the
-// block's corner rays (first and last bin of each angle at the band's first and
-// last row), widened by one column on each side for rounding and clamped to
-// [-2, n+1].  Every wave computes it redundantly (one corner per lane), so no
-// block synchronisation is needed.
 struct Window {
   int c0, c1;
 };
 
-__device__ __forceinline__ Window band_window(const FwdAngle& ca, bool cvalid, int cj, bool cfirst,
-                                              int rb, int re, int n) {
-  int lo = 1 << 30, hi = -(1 << 30);
-  if (cvalid) {
-    const int r = cfirst ? rb : re;
-    const double P = fma((double)r, ca.slope, fma((double)cj, ca.inv, ca.A0));
-    const int f = (int)fmin(fmax(floor(P), -1.0e9), 1.0e9);
-    lo = f - 1;
-    hi = f + 1;
+// Row range and per-band column windows of every block, computed once per
+// geometry (they depend on the geometry only).  Block (g, bx) covers angles
+// groups[g][0..8) and bins [32 bx, 32 bx + 31] (clipped to nb).
+//  - rows: [lo, hi], the union over the block's rays of the rows where the
+//    ray is within 1.5 columns of the image;
+//  - band b (rows [lo + b*BAND, min(lo + (b+1)*BAND - 1, hi)]): columns
+//    [c0, c1], the floor(P) range over the block's corner rays (first and
+//    last bin of each angle at the band's first and last row), widened by one
+//    column on each side for rounding and clamped to [-2, n+1].
+// Positions are linear in bin and row for each angle, so the corner rays
+// bound every ray of the block, and the row range's extremes over the bins
+// are at the first and last bin.
+__device__ __forceinline__ void ray_rows(const FwdAngle& ang, int j, int n, int& lo, int& hi) {
+  const double P0 = fma((double)j, ang.inv, ang.A0);
+  lo = n;
+  hi = -1;
+  if (ang.slope == 0.0) {
+    if (P0 >= -1.5 && P0 <= n + 0.5) { lo = 0; hi = n - 1; }
+  } else {
+    const double t1 = (-1.5 - P0) / ang.slope, t2 = (n + 0.5 - P0) / ang.slope;
+    const double tl = fmin(t1, t2), th = fmax(t1, t2);
+    lo = (int)fmin(fmax(0.0, ceil(tl)), (double)n);
+    hi = (int)fmax(fmin((double)(n - 1), floor(th)), -1.0);
   }
-  Window w;
-  w.c0 = iclamp(__builtin_amdgcn_readfirstlane(wave_min(lo)), -2, n);
-  w.c1 = iclamp(__builtin_amdgcn_readfirstlane(wave_max(hi)), -2, n) + 1;
-  return w;
+}
+
+__device__ __forceinline__ int corner_col(const FwdAngle& ang, int j, int r) {
+  const double P = fma((double)r, ang.slope, fma((double)j, ang.inv, ang.A0));
+  return (int)fmin(fmax(floor(P), -1.0e9), 1.0e9);
+}
+
+// One thread per (block, band); band index -1 (the first thread of a block's
+// row) stores the row range.
+__global__ __launch_bounds__(256) void k_fwd_windows(const FwdAngle* __restrict__ ang,
+                                                     const int* __restrict__ groups, int ngroups,
+                                                     int nbx, int n, int nb, int band, int maxb,
+                                                     int2* __restrict__ rows,
+                                                     int2* __restrict__ wins) {
+  const long long id = blockIdx.x * 256ll + threadIdx.x;
+  const long long total = (long long)ngroups * nbx * (maxb + 1);
+  if (id >= total) return;
+  const int blk = (int)(id / (maxb + 1));
+  const int b = (int)(id % (maxb + 1)) - 1;
+  const int g = blk / nbx, bx = blk % nbx;
+  const int jfirst = bx * kBins, jlast = min(jfirst + kBins - 1, nb - 1);
+  int lo = n, hi = -1;
+  for (int s = 0; s < kSlots; ++s) {
+    const int k = groups[g * kSlots + s];
+    if (k < 0) continue;
+    int l, h;
+    ray_rows(ang[k], jfirst, n, l, h);
+    if (h >= l) { lo = min(lo, l); hi = max(hi, h); }
+    ray_rows(ang[k], jlast, n, l, h);
+    if (h >= l) { lo = min(lo, l); hi = max(hi, h); }
+  }
+  if (b < 0) {
+    rows[blk] = make_int2(lo, hi);
+    return;
+  }
+  const int rb = lo + b * band;
+  int c0 = 0, c1 = 0;
+  if (hi >= lo && rb <= hi) {
+    const int re = min(rb + band - 1, hi);
+    int wl = 1 << 30, wh = -(1 << 30);
+    for (int s = 0; s < kSlots; ++s) {
+      const int k = groups[g * kSlots + s];
+      if (k < 0) continue;
+      const int cs[4] = {corner_col(ang[k], jfirst, rb), corner_col(ang[k], jfirst, re),
+                         corner_col(ang[k], jlast, rb), corner_col(ang[k], jlast, re)};
+      for (int i = 0; i < 4; ++i) {
+        wl = min(wl, cs[i] - 1);
+        wh = max(wh, cs[i] + 1);
+      }
+    }
+    c0 = iclamp(wl, -2, n);
+    c1 = iclamp(wh, -2, n) + 1;
+  }
+  wins[(size_t)blk * maxb + b] = make_int2(c0, c1);
 }
 
 template <typename T, int MODE>
@@ -250,9 +312,7 @@ __device__ __forceinline__ void forward_body(const FwdK<T>& a, const BlockPos bp
   double alpha_prev = 0.0;
   if constexpr (MODE == FWD_CGLS) alpha_prev = a.st->alpha;
   __shared__ T win[2][BAND * kStride];
-  __shared__ int sh_lo[kThreads / 64], sh_hi[kThreads / 64];
   const int t = threadIdx.x;
-  const int lane = t & 63, wv = t >> 6;
   const int n = a.n, nb = a.nb;
   const int g = bp.y;
   const int jfirst = bp.x * kBins;
@@ -272,40 +332,11 @@ __device__ __forceinline__ void forward_body(const FwdK<T>& a, const BlockPos bp
   const T* img = ang0.major ? a.imgTP : a.imgP;
   const __amdgpu_buffer_rsrc_t rs = image_rsrc(img, (size_t)n * a.ld * sizeof(T));
   const double P0 = fma((double)j, ang.inv, ang.A0);
-  // rows where this ray touches the image (with margin); block union
-  int lo = n, hi = -1;
-  if (valid) {
-    if (ang.slope == 0.0) {
-      if (P0 >= -1.5 && P0 <= n + 0.5) { lo = 0; hi = n - 1; }
-    } else {
-      const double t1 = (-1.5 - P0) / ang.slope, t2 = (n + 0.5 - P0) / ang.slope;
-      const double tl = fmin(t1, t2), th = fmax(t1, t2);
-      lo = (int)fmin(fmax(0.0, ceil(tl)), (double)n);
-      hi = (int)fmax(fmin((double)(n - 1), floor(th)), -1.0);
-    }
-  }
-  lo = wave_min(lo);
-  hi = wave_max(hi);
-  if (lane == 0) {
-    sh_lo[wv] = lo;
-    sh_hi[wv] = hi;
-  }
-  __syncthreads();
-#pragma unroll
-  for (int i = 0; i < kThreads / 64; ++i) {
-    lo = min(lo, sh_lo[i]);
-    hi = max(hi, sh_hi[i]);
-  }
-  lo = __builtin_amdgcn_readfirstlane(lo);
-  hi = __builtin_amdgcn_readfirstlane(hi);
-  // the corner ray this lane evaluates for the band windows
-  const int cc = lane & 31;
-  const int ck = a.groups[g * kSlots + (cc >> 2)];
-  const bool cvalid = ck >= 0;
-  const FwdAngle ca = a.ang[cvalid ? ck : k0];
-  const int cj = ((cc >> 1) & 1) ? jlast : jfirst;
-  const bool cfirst = (cc & 1) == 0;
-
+  // rows the block's rays touch and the column window of each band (setup table)
+  const int blk = g * a.nbx + bp.x;
+  const int2 rr = a.rows[blk];
+  const int lo = rr.x, hi = rr.y;
+  const int2* __restrict__ bandwin = a.wins + (size_t)blk * a.maxb;
   const T B = wB<T>(ang), C = wC<T>(ang), Wm = wM<T>(ang);
   const float Bq = (float)(-ang.B * 2.3283064365386963e-10), Cq = (float)(ang.C + 0.5 * ang.B);
   T acc0 = T(0), acc1 = T(0);
@@ -322,7 +353,8 @@ __device__ __forceinline__ void forward_body(const FwdK<T>& a, const BlockPos bp
   Window wcur{0, 0};
   int cur_shift = 0;   // window start the walker's columns are currently relative to
   if (nbands > 0) {
-    wcur = band_window(ca, cvalid, cj, cfirst, lo, min(lo + BAND - 1, hi), n);
+    const int2 w0 = bandwin[0];
+    wcur = Window{w0.x, w0.y};
     if (wcur.c1 - wcur.c0 + 1 <= kWinCols) {
 #pragma unroll
       for (int i = 0; i < STAGE_PER; ++i) {
@@ -345,7 +377,8 @@ __device__ __forceinline__ void forward_body(const FwdK<T>& a, const BlockPos bp
     bool next_lds = false;
     if (more) {
       const int rb2 = rb + BAND;
-      wnext = band_window(ca, cvalid, cj, cfirst, rb2, min(rb2 + BAND - 1, hi), n);
+      const int2 w1 = bandwin[bnd + 1];
+      wnext = Window{w1.x, w1.y};
       next_lds = wnext.c1 - wnext.c0 + 1 <= kWinCols;
       if (next_lds) {
 #pragma unroll
@@ -507,6 +540,10 @@ FwdK<T> make_args(const Geometry& g, const FwdArgs& a) {
   k.R = (const T*)a.R;
   k.ang = g.d_fwd;
   k.groups = g.d_groups;
+  k.rows = (const int2*)g.d_fwd_rows;
+  k.wins = (const int2*)g.d_fwd_wins;
+  k.nbx = (g.nb + kBins - 1) / kBins;
+  k.maxb = g.fwd_maxb;
   k.st = a.st;
   k.red = a.red;
   k.count = a.count;
@@ -540,6 +577,20 @@ void fwd_dispatch(const Geometry& g, FwdMode mode, const FwdArgs& a, hipStream_t
 }
 
 }  // namespace
+
+void build_forward_windows(Geometry& g, hipStream_t st) {
+  const int band = g.f64 ? kBand<double> : kBand<float>;
+  const int nbx = (g.nb + kBins - 1) / kBins;
+  g.fwd_maxb = (g.n + band - 1) / band;
+  const size_t nblk = (size_t)g.ngroups * nbx;
+  HIP_CHECK(hipMalloc(&g.d_fwd_rows, sizeof(int2) * nblk));
+  HIP_CHECK(hipMalloc(&g.d_fwd_wins, sizeof(int2) * nblk * g.fwd_maxb));
+  const long long total = (long long)nblk * (g.fwd_maxb + 1);
+  hipLaunchKernelGGL(k_fwd_windows, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st,
+                     g.d_fwd, g.d_groups, g.ngroups, nbx, g.n, g.nb, band, g.fwd_maxb,
+                     (int2*)g.d_fwd_rows, (int2*)g.d_fwd_wins);
+  HIP_CHECK(hipGetLastError());
+}
 
 int forward_blocks(const Geometry& g) { return ((g.nb + kBins - 1) / kBins) * g.ngroups; }
 

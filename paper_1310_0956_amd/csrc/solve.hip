@@ -83,8 +83,13 @@ size_t cgls_workspace_bytes(const reco_geometry_desc& d) {
 size_t geometry_bytes(const reco_geometry_desc& d) {
   const size_t es = d.dtype == RECO_F64 ? 8 : 4;
   const size_t N = (size_t)d.n * d.n;
+  // forward block tables: at most (m + 7) / 8 + 3 angle groups (runs of up to
+  // 8 angles, broken at the two walk-axis changes)
+  const size_t groups = (size_t)(d.n_angles + 7) / 8 + 3;
+  const size_t bands = (size_t)(d.n + 15) / 16;
+  const size_t blocks = groups * (size_t)((d.n_bins + 31) / 32);
   return (sizeof(FwdAngle) + sizeof(BwdAngle) + 8 * sizeof(int)) * (size_t)(d.n_angles + 8) +
-         N * (8 + es) + 4096;
+         blocks * (bands + 1) * 8 + N * (8 + es) + 4096;
 }
 
 void return_workspace(Geometry& g, Workspace* w) {
