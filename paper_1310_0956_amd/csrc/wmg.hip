@@ -13,9 +13,9 @@
 // d_q = ||W H_L^T e_q||^2 is the diagonal of the Galerkin operators of the
 // coarsest subproblems in the packet basis (eq. galerkin).  It is computed once
 // per geometry, tile by tile: for every angle and every detector bin crossing a
-// tile, the tile's weights are Walsh-transformed across the lanes of a wave and
-// their squares are accumulated in float64 by the wave that owns the tile, in
-// a fixed order (deterministic, no atomics).
+// tile, the tile's weights are Walsh-transformed by the lanes that hold the
+// tile (one row per lane); their squares are summed per angle and added to
+// float64 sums, in a fixed order (deterministic, no atomics).
 #include "device_common.h"
 #include "timing.h"
 
@@ -220,38 +220,74 @@ void wmg_launch(const Geometry& g, WmgMode mode, const WmgArgs& a, hipStream_t s
   }
 }
 
+// Value of lane (lane ^ MASK) for MASK < 16, with DPP lane moves inside a row
+// of 16 lanes: xor 1 and 2 by quad permutes, 8 by a row rotation by 8, 4 by a
+// half-row mirror (i -> i ^ 7) followed by the quad permute i -> i ^ 3.
+// Larger masks use a general lane permute.
+template <int MASK>
+__device__ __forceinline__ int xor_lane_b32(int v) {
+  if constexpr (MASK == 1) return __builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, true);
+  else if constexpr (MASK == 2) return __builtin_amdgcn_mov_dpp(v, 0x4E, 0xF, 0xF, true);
+  else if constexpr (MASK == 4)
+    return __builtin_amdgcn_mov_dpp(__builtin_amdgcn_mov_dpp(v, 0x141, 0xF, 0xF, true), 0x1B, 0xF,
+                                    0xF, true);
+  else if constexpr (MASK == 8) return __builtin_amdgcn_mov_dpp(v, 0x128, 0xF, 0xF, true);
+  else return __shfl_xor(v, MASK, 64);
+}
+
+template <int MASK>
+__device__ __forceinline__ float xor_lane(float v) {
+  return __builtin_bit_cast(float, xor_lane_b32<MASK>(__builtin_bit_cast(int, v)));
+}
+template <int MASK>
+__device__ __forceinline__ double xor_lane(double v) {
+  const long long b = __builtin_bit_cast(long long, v);
+  const int lo = xor_lane_b32<MASK>((int)b), hi = xor_lane_b32<MASK>((int)(b >> 32));
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned)lo);
+}
+
+// y stages of the transform: stage b exchanges with lane y ^ 2^b
+template <typename T, int L, int B = 0>
+__device__ __forceinline__ void y_stages(T (&w)[1 << L], const T (&sgn)[L > 0 ? L : 1]) {
+  if constexpr (B < L) {
+#pragma unroll
+    for (int x = 0; x < (1 << L); ++x) w[x] = fma(sgn[B], w[x], xor_lane<(1 << B)>(w[x]));
+    y_stages<T, L, B + 1>(w, sgn);
+  }
+}
+
 // --------------------------- packet diagonal --------------------------------
-// Lane layout: a tile of S = T*T pixels is spread over the 64 lanes of a wave
-// (E = S/64 pixels per lane when S >= 64, element e = r*64 + lane) or several
-// tiles share a wave (G = 64/S tiles, element e = lane % S).  Element e is the
-// tile pixel (ly, lx) = (e >> L, e & (T-1)).
+// Lane layout: a tile of T x T pixels (T = 2^L) is held by T consecutive
+// lanes, lane y holding the tile's row y with its T pixels in registers, so a
+// wave holds 64 / T tiles.  For every angle and every bin that reaches a
+// tile, the tile's weights are Walsh-Hadamard transformed (x stages within
+// the registers of a lane, y stages across the tile's lanes); the squares are
+// summed per angle in the tile's precision and added to float64 sums, in a
+// fixed order (deterministic, no atomics).
+// The butterflies keep the low element as u + v and the high one as u - v, so
+// the coefficients land in the in-place layout of the apply.
 template <typename T, int L>
 __global__ __launch_bounds__(256) void k_packet_diag(const BwdAngle* __restrict__ ang, double* d64,
                                                      T* dT, int n, int m, int nb, double h) {
   constexpr int Tt = 1 << L;
-  constexpr int S = Tt * Tt;
-  constexpr int E = S >= 64 ? S / 64 : 1;
-  constexpr int G = S >= 64 ? 1 : 64 / S;
-  constexpr int LB = S >= 64 ? 6 : 2 * L;   // element bits held across lanes
+  constexpr int TPW = 64 / Tt;   // tiles per wave
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int tiles_x = n / Tt;
   const int ntiles = tiles_x * tiles_x;
-  const int tile = (blockIdx.x * 4 + wv) * G + (S >= 64 ? 0 : lane / S);
+  const int tile = (blockIdx.x * 4 + wv) * TPW + lane / Tt;
+  const int y = lane & (Tt - 1);
   const bool active = tile < ntiles;
   const int tyT = active ? tile / tiles_x : 0, txT = active ? tile % tiles_x : 0;
   const double hc = 0.5 * (n - 1), hb = 0.5 * (nb - 1);
   const double Xt = txT * Tt + 0.5 * (Tt - 1) - hc;   // tile centre, pixel units
   const double Yt = tyT * Tt + 0.5 * (Tt - 1) - hc;
-  T dXp[E], dYp[E];
+  const T dY = T(y - 0.5 * (Tt - 1));
+  T sgn[L > 0 ? L : 1];   // y stage b: +1 keeps u + v (low lane), -1 gives u - v (high lane)
 #pragma unroll
-  for (int r = 0; r < E; ++r) {
-    const int e = (S >= 64) ? (r * 64 + lane) : (lane % S);
-    dXp[r] = T((e & (Tt - 1)) - 0.5 * (Tt - 1));
-    dYp[r] = T((e >> L) - 0.5 * (Tt - 1));
-  }
-  double acc[E];
+  for (int b = 0; b < L; ++b) sgn[b] = ((y >> b) & 1) ? T(-1) : T(1);
+  double acc[Tt];
 #pragma unroll
-  for (int r = 0; r < E; ++r) acc[r] = 0.0;
+  for (int x = 0; x < Tt; ++x) acc[x] = 0.0;
 
   for (int k = 0; k < m; ++k) {
     const BwdAngle A = ang[k];
@@ -261,57 +297,51 @@ __global__ __launch_bounds__(256) void k_packet_diag(const BwdAngle* __restrict_
     T c, s, Bq, Cq, Wm;
     if constexpr (sizeof(T) == 4) { c = A.cf; s = A.sf; Bq = A.inv_uv_f; Cq = A.cc_f; Wm = A.Wmaxf; }
     else { c = A.c; s = A.s; Bq = A.inv_uv_d; Cq = A.cc_d; Wm = A.Wmax; }
-    T Jp[E];
+    const T by = fma(dY, s, rel);
+    T Jp[Tt];
 #pragma unroll
-    for (int r = 0; r < E; ++r) Jp[r] = fma(dXp[r], c, fma(dYp[r], s, rel));
+    for (int x = 0; x < Tt; ++x) Jp[x] = fma(T(x - 0.5 * (Tt - 1)), c, by);
     // bins with nonzero weight satisfy |jj - rel| < Tt * (u+v)/2 (+1 for rel in [0,1))
     const double reach = Tt * A.half_u_plus_v;
     const int jlo = (int)floor(-reach), jhi = (int)ceil(1.0 + reach);
     const int jb = (int)jbase;
+    T part[Tt];   // this angle's sums of squares (a few dozen terms)
+#pragma unroll
+    for (int x = 0; x < Tt; ++x) part[x] = T(0);
     for (int jj = jlo; jj <= jhi; ++jj) {
       const int j = jb + jj;
       const bool inb = active && j >= 0 && j < nb;
-      T w[E];
+      T w[Tt];
 #pragma unroll
-      for (int r = 0; r < E; ++r) {
-        const T dist = fabs(T(jj) - Jp[r]);
-        w[r] = inb ? clamp01<T>(fma(-dist, Bq, Cq), Wm) : T(0);
+      for (int x = 0; x < Tt; ++x) {
+        const T dist = fabs(T(jj) - Jp[x]);
+        w[x] = inb ? clamp01<T>(fma(-dist, Bq, Cq), Wm) : T(0);
       }
-      // Walsh-Hadamard transform over the tile's S elements
 #pragma unroll
-      for (int b = 0; b < 2 * L; ++b) {
-        if (b < LB) {
+      for (int b = 0; b < L; ++b) {   // along x, in registers
 #pragma unroll
-          for (int r = 0; r < E; ++r) {
-            const T o = __shfl_xor(w[r], 1 << b, 64);
-            w[r] = (lane >> b) & 1 ? o - w[r] : w[r] + o;
-          }
-        } else {
-          const int rb = 1 << (b - LB);
-#pragma unroll
-          for (int r = 0; r < E; ++r) {
-            if (!(r & rb)) {
-              const T u = w[r], v = w[r | rb];
-              w[r] = u + v;
-              w[r | rb] = u - v;
-            }
+        for (int x = 0; x < Tt; ++x) {
+          if (!(x & (1 << b))) {
+            const T u = w[x], v = w[x | (1 << b)];
+            w[x] = u + v;
+            w[x | (1 << b)] = u - v;
           }
         }
       }
+      y_stages<T, L>(w, sgn);   // along y, across the tile's lanes
 #pragma unroll
-      for (int r = 0; r < E; ++r) {
-        const double q = (double)w[r];
-        acc[r] = fma(q, q, acc[r]);
-      }
+      for (int x = 0; x < Tt; ++x) part[x] = fma(w[x], w[x], part[x]);
     }
+#pragma unroll
+    for (int x = 0; x < Tt; ++x) acc[x] += (double)part[x];
   }
   if (active) {
     const double scale = h * h / (double)(1u << (2 * L));
+    const int iy = tyT * Tt + y;
 #pragma unroll
-    for (int r = 0; r < E; ++r) {
-      const int e = (S >= 64) ? (r * 64 + lane) : (lane % S);
-      const int iy = tyT * Tt + (e >> L), ix = txT * Tt + (e & (Tt - 1));
-      const double v = acc[r] * scale;
+    for (int x = 0; x < Tt; ++x) {
+      const int ix = txT * Tt + x;
+      const double v = acc[x] * scale;
       d64[(size_t)iy * n + ix] = v;
       dT[(size_t)iy * n + ix] = (T)v;
     }
@@ -320,10 +350,8 @@ __global__ __launch_bounds__(256) void k_packet_diag(const BwdAngle* __restrict_
 
 template <typename T, int L>
 void diag_launch_L(Geometry& g, hipStream_t st) {
-  constexpr int S = (1 << L) * (1 << L);
-  constexpr int G = S >= 64 ? 1 : 64 / S;
   const int ntiles = (g.n >> L) * (g.n >> L);
-  const int tiles_per_block = 4 * G;
+  const int tiles_per_block = 4 * (64 >> L);
   const int blocks = (ntiles + tiles_per_block - 1) / tiles_per_block;
   TimedLaunch tl(TK_PACKET_DIAG, st);
   hipLaunchKernelGGL((k_packet_diag<T, L>), dim3(blocks), dim3(256), 0, st, g.d_bwd, g.d_diag64,
