@@ -165,21 +165,16 @@ __device__ __forceinline__ void wht16(T (*tile)[kTile + 1]) {
   }
 }
 
-// z = H^T diag(4^-L / (d + lambda)) H s on the 16 x 16 tile at (x0, y0),
-// in place (1/0 := 0).  Threads t < 256 own pixel (t & 15, t >> 4).
+// z = H^T diag(4^-L / (d + lambda)) H s on the 16 x 16 tile, in place
+// (1/0 := 0).  Threads t < 256 own pixel (t & 15, t >> 4) and pass that
+// pixel's d + lambda (0 outside the image).
 template <typename T, int L>
-__device__ __forceinline__ void wmg_tile(T (*tile)[kTile + 1], const T* __restrict__ d, int n,
-                                         int x0, int y0, double lambda) {
+__device__ __forceinline__ void wmg_tile(T (*tile)[kTile + 1], double dl) {
   wht16<T, L>(tile);
   const int t = threadIdx.x;
   if (t < kTile * kTile) {
     const int px = t & (kTile - 1), py = t / kTile;
-    const int ix = x0 + px, iy = y0 + py;
-    double inv = 0.0;
-    if (ix < n && iy < n) {
-      const double dd = (double)d[(size_t)iy * n + ix] + lambda;
-      inv = dd != 0.0 ? (1.0 / (double)(1u << (2 * L))) / dd : 0.0;
-    }
+    const double inv = dl != 0.0 ? (1.0 / (double)(1u << (2 * L))) / dl : 0.0;
     tile[py][px] = (T)((double)tile[py][px] * inv);
   }
   __syncthreads();
@@ -255,6 +250,30 @@ __device__ __forceinline__ void backward_body(const BwdK<T>& a, const BlockPos p
     if (more) stage_store<T, MODE>(pre, win[grp][nxt], alpha, t);
     __syncthreads();
   }
+  // CGLS: issue the epilogue's global loads before the partial-sum barrier
+  T z_in[2] = {T(0), T(0)}, p_in[2] = {T(0), T(0)}, x_in[2] = {T(0), T(0)};
+  double d_own = 0.0;   // d + lambda of the WMG pixel of threads < 256
+  if constexpr (MODE == BWD_CGLS || MODE == BWD_CGLS_INIT) {
+    if (grp == 0) {
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        const int iy = q ? iy1 : iy0;
+        if (ix < n && iy < n) {
+          const size_t px = (size_t)iy * n + ix;
+          if constexpr (MODE == BWD_CGLS) {
+            z_in[q] = a.zP[(size_t)iy * a.ld + ix + kPad];
+            p_in[q] = a.p[px];
+          }
+          x_in[q] = a.xo[px];
+        }
+      }
+    }
+    const int tt = threadIdx.x;
+    if (a.fuse && !a.identity && tt < kTile * kTile) {
+      const int ix2 = pos.x * kTile + (tt & (kTile - 1)), iy2 = pos.y * kTile + tt / kTile;
+      if (ix2 < n && iy2 < n) d_own = (double)a.d[(size_t)iy2 * n + ix2] + a.st->lambda;
+    }
+  }
   part[grp][0][t] = acc0;
   part[grp][1][t] = acc1;
   __syncthreads();
@@ -286,13 +305,12 @@ __device__ __forceinline__ void backward_body(const BwdK<T>& a, const BlockPos p
           const size_t px = (size_t)iy * n + ix;
           T xn;
           if constexpr (MODE == BWD_CGLS) {
-            const double z = (double)a.zP[(size_t)iy * a.ld + ix + kPad];
-            pv = (T)(z + beta * (double)a.p[px]);
+            pv = (T)((double)z_in[q] + beta * (double)p_in[q]);
             a.p[px] = pv;
-            xn = (T)((double)a.xo[px] + alpha * (double)pv);
+            xn = (T)((double)x_in[q] + alpha * (double)pv);
             a.xo[px] = xn;
           } else {
-            xn = a.xo[px];
+            xn = x_in[q];
           }
           sv = (T)(bp[q] - lambda * (double)xn);
           if (!a.fuse) a.out[px] = sv;
@@ -313,11 +331,11 @@ __device__ __forceinline__ void backward_body(const BwdK<T>& a, const BlockPos p
     __syncthreads();
     if (!a.identity) {
       switch (a.L) {
-        case 0: wmg_tile<T, 0>(stile, a.d, n, x0, y0, lambda); break;
-        case 1: wmg_tile<T, 1>(stile, a.d, n, x0, y0, lambda); break;
-        case 2: wmg_tile<T, 2>(stile, a.d, n, x0, y0, lambda); break;
-        case 3: wmg_tile<T, 3>(stile, a.d, n, x0, y0, lambda); break;
-        default: wmg_tile<T, 4>(stile, a.d, n, x0, y0, lambda); break;
+        case 0: wmg_tile<T, 0>(stile, d_own); break;
+        case 1: wmg_tile<T, 1>(stile, d_own); break;
+        case 2: wmg_tile<T, 2>(stile, d_own); break;
+        case 3: wmg_tile<T, 3>(stile, d_own); break;
+        default: wmg_tile<T, 4>(stile, d_own); break;
       }
     }
     double v[4] = {0.0, 0.0, 0.0, 0.0};   // <s,z>, ||s||^2, ||z||^2, <z,p>
