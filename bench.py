@@ -10,7 +10,9 @@ once beforehand, reported as setup).
 
 Prints one JSON line with the throughput, the per-kernel roofline of the
 dominant kernel (HIP-event timed inside the measured steps) and the CPU
-float64 oracle timed on a bounded sample on the host.
+float64 oracle timed on a bounded sample on the host; further objects report
+the 512^2 solver comparison (CGLS, WMG-CGLS, WMG-GMRES(30), SIRT), the batched
+and served workloads and the 2048^2 reconstruction.
 """
 import argparse
 import hashlib
@@ -49,6 +51,8 @@ def parse():
     ap.add_argument("--serve-budget-gib", type=float, default=64.0)
     ap.add_argument("--serve-slots", type=int, default=64)
     ap.add_argument("--no-ct2048", action="store_true", help="skip the 2048^2 leg")
+    ap.add_argument("--no-solvers", action="store_true",
+                    help="skip the 512^2 solver comparison (CGLS, GMRES, SIRT)")
     ap.add_argument("--profile-only", action="store_true",
                     help="only run the timed steps (for rocprofv3)")
     return ap.parse_args()
@@ -277,6 +281,29 @@ def serve_leg(reco, torch, count, rate, budget_gib, slots):
     }
 
 
+def solvers_leg(reco, torch, g, sinos):
+    """The four solvers of the 512^2 workload to rel-res 1e-3 (iteration cap
+    1000): iterations, applications of W^T W and time per reconstruction."""
+    out = {}
+    x = g.new_image()
+    runs = [("cgls", lambda b: g.solve_cgls(b, x=x, tol=1e-3, precond=reco.PRECOND_NONE)),
+            ("wmg_cgls", lambda b: g.solve_cgls(b, x=x, tol=1e-3)),
+            ("wmg_gmres30", lambda b: g.solve_gmres(b, x=x, tol=1e-3, restart=30)),
+            ("sirt", lambda b: g.solve_sirt(b, x=x, tol=1e-3, max_iter=1000))]
+    for name, fn in runs:
+        fn(sinos[0])
+        torch.cuda.synchronize()
+        reps = 1 if name == "sirt" else 3
+        t0 = time.perf_counter()
+        infos = [fn(sinos[i % len(sinos)])[1] for i in range(reps)]
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) / reps * 1e3
+        out[name] = {"iters": infos[-1]["iters"], "matvecs": infos[-1]["matvecs"],
+                     "status": infos[-1]["status"], "relres": round(infos[-1]["relres"], 6),
+                     "ms_per_recon": round(ms, 3)}
+    return out
+
+
 def ct2048_leg(reco, torch):
     """2048^2 image, 2048 angles x 2897 bins, 5-level WMG-CGLS to rel-res 1e-3."""
     t0 = time.perf_counter()
@@ -426,6 +453,8 @@ def main():
         "kernel_avg_ms": {k: round(v, 5) for k, v in avg_ms.items()},
         "roofline": roofline,
     }
+    if not args.no_solvers:
+        result["solvers_ct512"] = solvers_leg(reco, torch, g, sinos)
     if args.batch > 0:
         result["batch"] = batch_leg(reco, torch, args.batch)
     if args.serve > 0:
