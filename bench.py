@@ -16,6 +16,7 @@ and served workloads and the 2048^2 reconstruction.
 """
 import argparse
 import hashlib
+import gc
 import json
 import math
 import os
@@ -50,6 +51,9 @@ def parse():
     ap.add_argument("--serve-rate", type=float, default=20.0, help="arrivals per second")
     ap.add_argument("--serve-budget-gib", type=float, default=64.0)
     ap.add_argument("--serve-slots", type=int, default=64)
+    ap.add_argument("--serve-extra", type=int, default=1,
+                    help="also serve at 35/s and with a 1 GiB budget (0: skip)")
+    ap.add_argument("--no-tiny64", action="store_true", help="skip the 64^2 float64 leg")
     ap.add_argument("--no-ct2048", action="store_true", help="skip the 2048^2 leg")
     ap.add_argument("--no-solvers", action="store_true",
                     help="skip the 512^2 solver comparison (CGLS, GMRES, SIRT)")
@@ -304,6 +308,36 @@ def solvers_leg(reco, torch, g, sinos):
     return out
 
 
+def tiny64_leg(reco, torch):
+    """64^2, 90 angles x 64 bins, 10-ellipse noiseless phantom, float64:
+    50 iterations each of SIRT, CGLS and 2-level WMG-CGLS."""
+    import numpy as np
+    import inputs
+    g = reco.Geometry(64, 90, 64, 2, reco.F64)
+    x = torch.from_numpy(inputs.ellipse_phantom(64, 10, 0)).cuda()
+    b = g.project(x)
+    torch.cuda.synchronize()
+    out = {"workload": "tiny64: 64x64, 90 angles x 64 bins, 10-ellipse noiseless phantom, float64, "
+                       "50 iterations each"}
+    xs = g.new_image()
+    for name, fn in [("sirt", lambda: g.solve_sirt(b, x=xs, fixed_iters=50)),
+                     ("cgls", lambda: g.solve_cgls(b, x=xs, fixed_iters=50,
+                                                   precond=reco.PRECOND_NONE)),
+                     ("wmg_cgls", lambda: g.solve_cgls(b, x=xs, fixed_iters=50))]:
+        fn()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(3):
+            t0 = time.perf_counter()
+            _, info = fn()
+            torch.cuda.synchronize()
+            ts.append((time.perf_counter() - t0) * 1e3)
+        err = float(torch.linalg.norm(xs - x) / torch.linalg.norm(x))
+        out[name] = {"ms_median_of_3": round(sorted(ts)[1], 3),
+                     "relres": float("%.4g" % info["relres"]), "rel_error_vs_phantom": round(err, 5)}
+    return out
+
+
 def ct2048_leg(reco, torch):
     """2048^2 image, 2048 angles x 2897 bins, 5-level WMG-CGLS to rel-res 1e-3."""
     t0 = time.perf_counter()
@@ -456,12 +490,39 @@ def main():
     if not args.no_solvers:
         result["solvers_ct512"] = solvers_leg(reco, torch, g, sinos)
     if args.batch > 0:
+        # the same workload, 8 reconstructions per batched solve (the headline
+        # value above is one reconstruction at a time)
+        xs8 = [g.new_image() for _ in range(8)]
+        bs8 = [sinos[i % len(sinos)] for i in range(8)]
+        reco.solve_batch([g] * 8, bs8, xs8, tol=w["tol"])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        reps = 5
+        for _ in range(reps):
+            infos8 = reco.solve_batch([g] * 8, bs8, xs8, tol=w["tol"])
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / reps
+        result["ct512_batched8"] = {"recons_per_s": round(8 / dt, 3),
+                                    "ms_per_batch": round(dt * 1e3, 3),
+                                    "all_ok": all(i["status"] == "ok" for i in infos8)}
+    if args.batch > 0:
         result["batch"] = batch_leg(reco, torch, args.batch)
     if args.serve > 0:
         result["serving"] = serve_leg(reco, torch, args.serve, args.serve_rate,
                                       args.serve_budget_gib, args.serve_slots)
+        if args.serve_extra:
+            # a higher arrival rate, and a small device-memory budget that
+            # forces admission queueing
+            result["serving_rate35"] = serve_leg(reco, torch, args.serve, 35.0,
+                                                 args.serve_budget_gib, args.serve_slots)
+            result["serving_budget1g"] = serve_leg(reco, torch, args.serve, args.serve_rate,
+                                                   1.0, args.serve_slots)
     if not args.no_ct2048:
         result["ct2048"] = ct2048_leg(reco, torch)
+    if not args.no_tiny64:
+        gc.collect()
+        torch.cuda.synchronize()
+        result["tiny64_f64"] = tiny64_leg(reco, torch)
     if not args.no_cpu_baseline:
         solved, t_sum, cpu_iters = cpu_baseline(args)
         result["cpu_baseline"] = {
