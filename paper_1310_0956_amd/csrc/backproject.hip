@@ -4,9 +4,12 @@
 // waves (two pixels per thread), each looping over its share of the angle
 // chunks (32 angles each); their partial sums are added in group order at the
 // end (no atomics).  For each angle of a chunk the tile's
-// detector footprint (at most 26 bins for a 16-pixel tile) is staged in LDS,
+// detector footprint (at most 23 bins for a 16-pixel tile) is staged in LDS,
 // double buffered: the next chunk's window is fetched into registers while the
-// current one is consumed.  Every pixel then reads its two candidate
+// current one is consumed.  The per-angle constants (window start, tile-centre
+// bin coordinate, direction cosines, weight coefficients) sit in a three-deep
+// LDS ring, filled from angle records fetched two chunks ahead, so no chunk
+// waits on them.  Every pixel then reads its two candidate
 // bins floor(J) and floor(J)+1, J being the bin coordinate of the pixel
 // centre, and weights them with the same exact intersection length w(t) the
 // forward projector uses (trapezoid in the ray offset t), so the result is the
@@ -22,10 +25,12 @@ namespace {
 constexpr int kTile = 16;    // pixels per tile side
 constexpr int kThreads = 128; // two pixels per thread: rows ty and ty + 8
 constexpr int kChunk = 32;    // angles per LDS stage
-constexpr int kWin = 28;      // bins staged per angle: pixel centres lie within
-                              // 7.5 * sqrt(2) < 11 bins of the tile centre, so
-                              // floor(J) + 1 <= kHalf + 1 + 11 < kWin
-constexpr int kHalf = 12;     // window starts kHalf bins below the tile centre
+constexpr int kWin = 24;      // bins staged per angle: pixel centres lie within
+                              // 7.5 (|c| + |s|) <= 7.5 sqrt(2) < 10.61 bins of the
+                              // tile centre, so with the window starting kHalf
+                              // bins below floor(tile centre) every pixel has
+                              // 0.39 < J < 22.61, i.e. 0 <= floor(J), floor(J) + 1 <= 23
+constexpr int kHalf = 11;     // window starts kHalf bins below the tile centre
 constexpr int kPerThread = kChunk * kWin / kThreads;
 
 template <typename T>
@@ -51,7 +56,7 @@ struct BwdK {
   double sa, sx, sf; // out = sa*(W^T r) + sx*xin + sf*fin
 };
 
-// Per-angle constants staged in LDS for the current chunk.
+// Per-angle constants of the current tile, in an LDS ring three chunks deep.
 template <typename T>
 struct Meta {
   T base;   // bin coordinate of the tile centre minus the window start
@@ -60,17 +65,76 @@ struct Meta {
   int jw;   // first bin of the window
 };
 
+// The fields of the angle records a chunk's ring entries are filled from,
+// fetched by the first wave of each angle group before their use: lane i < 32
+// holds the float64 cosines (c, s) of the chunk's angle i, lane 32 + i its
+// weight coefficients (B, C0, C1, Wm), in the same registers.
 template <typename T>
-__device__ __forceinline__ void fill_meta(Meta<T>& M, const BwdAngle& A, double Xc, double Yc,
-                                          double hb) {
-  const double Jc = fma(Xc, A.c, fma(Yc, A.s, hb));
-  const double fl = floor(Jc);
-  M.jw = (int)fl - kHalf;
-  M.base = (T)((Jc - fl) + kHalf);
-  if constexpr (sizeof(T) == 4) {
-    M.c = A.cf; M.s = A.sf; M.B = A.Bf; M.C0 = A.C0f; M.C1 = A.C1f; M.Wm = A.Wmaxf;
-  } else {
-    M.c = A.c; M.s = A.s; M.B = A.B; M.C0 = A.C0; M.C1 = A.C1; M.Wm = A.Wmax;
+struct Raw {
+  static constexpr int kWords = sizeof(T) == 4 ? 4 : 8;
+  unsigned w[kWords];
+};
+
+// Called by the group's first wave (t < 64) for the chunk starting at angle k0.
+template <typename T>
+__device__ __forceinline__ void load_raw(Raw<T>& r, const BwdAngle* __restrict__ ang, int k0,
+                                         int t, int m) {
+  const int k = k0 + (t & 31);
+  if (k < m) {
+    const BwdAngle& A = ang[k];
+    const void* src;
+    if constexpr (sizeof(T) == 4) src = t < 32 ? (const void*)&A.c : (const void*)&A.Bf;
+    else src = t < 32 ? (const void*)&A.c : (const void*)&A.B;
+    const uint2* p = (const uint2*)src;   // 8-byte aligned fields
+#pragma unroll
+    for (int i = 0; i < Raw<T>::kWords / 2; ++i) {
+      const uint2 v = p[i];
+      r.w[2 * i] = v.x;
+      r.w[2 * i + 1] = v.y;
+    }
+  }
+}
+
+__device__ __forceinline__ double bits_to_double(unsigned lo, unsigned hi) {
+  return __hiloint2double((int)hi, (int)lo);
+}
+
+// A wave-uniform float64 held in scalar registers (vector arithmetic leaves
+// its results in vector registers).
+__device__ __forceinline__ double uniform(double v) {
+  return __hiloint2double(__builtin_amdgcn_readfirstlane(__double2hiint(v)),
+                          __builtin_amdgcn_readfirstlane(__double2loint(v)));
+}
+
+// Ring entries of the chunk starting at angle k0 from its records (all lanes
+// of the group's first wave take part; lanes t < 32 write entry t).  The
+// float cosines are the float64 ones rounded to nearest, as in the table.
+template <typename T>
+__device__ __forceinline__ void fill_meta(Meta<T>* __restrict__ ring, const Raw<T>& r, int k0,
+                                          int t, int m, double Xc, double Yc, double hb) {
+  Raw<T> up;
+#pragma unroll
+  for (int i = 0; i < Raw<T>::kWords; ++i) up.w[i] = __shfl_down(r.w[i], 32, 64);
+  if (t < kChunk && k0 + t < m) {
+    const double c = bits_to_double(r.w[0], r.w[1]), s = bits_to_double(r.w[2], r.w[3]);
+    Meta<T>& M = ring[t];
+    const double Jc = fma(Xc, c, fma(Yc, s, hb));
+    const double fl = floor(Jc);
+    M.jw = (int)fl - kHalf;
+    M.base = (T)((Jc - fl) + kHalf);
+    M.c = (T)c;
+    M.s = (T)s;
+    if constexpr (sizeof(T) == 4) {
+      M.B = __uint_as_float(up.w[0]);
+      M.C0 = __uint_as_float(up.w[1]);
+      M.C1 = __uint_as_float(up.w[2]);
+      M.Wm = __uint_as_float(up.w[3]);
+    } else {
+      M.B = bits_to_double(up.w[0], up.w[1]);
+      M.C0 = bits_to_double(up.w[2], up.w[3]);
+      M.C1 = bits_to_double(up.w[4], up.w[5]);
+      M.Wm = bits_to_double(up.w[6], up.w[7]);
+    }
   }
 }
 
@@ -198,7 +262,7 @@ __device__ __forceinline__ void backward_body(const BwdK<T>& a, const BlockPos p
     beta = a.st->beta;
   }
   __shared__ T win[G][2][kChunk * kWin];
-  __shared__ Meta<T> meta[G][2][kChunk];
+  __shared__ Meta<T> meta[G][3][kChunk];
   // the groups' partial sums reuse the window memory once the angle loop is done
   static_assert(G * 2 * kThreads <= G * 2 * kChunk * kWin, "partials must fit in the window");
   T (*part)[2][kThreads] = reinterpret_cast<T (*)[2][kThreads]>(&win[0][0][0]);
@@ -208,48 +272,70 @@ __device__ __forceinline__ void backward_body(const BwdK<T>& a, const BlockPos p
   const int ix = pos.x * kTile + tx;
   const int iy0 = pos.y * kTile + ty, iy1 = iy0 + 8;
   const int n = a.n, nb = a.nb, m = a.m;
-  const double hc = 0.5 * (n - 1), hb = 0.5 * (nb - 1);
-  const double Xc = pos.x * kTile + 0.5 * (kTile - 1) - hc;
-  const double Yc = pos.y * kTile + 0.5 * (kTile - 1) - hc;
+  const double hc = 0.5 * (n - 1), hb = uniform(0.5 * (nb - 1));
+  const double Xc = uniform(pos.x * kTile + 0.5 * (kTile - 1) - hc);
+  const double Yc = uniform(pos.y * kTile + 0.5 * (kTile - 1) - hc);
   const T dX = T(tx) - T(0.5 * (kTile - 1)), dY = T(ty) - T(0.5 * (kTile - 1));
   T acc0 = T(0), acc1 = T(0);
   const int nchunks = (m + kChunk - 1) / kChunk;
   const int steps = (nchunks + G - 1) / G;     // chunk steps, equal for every group
-  // prologue: this group's first chunk straight into LDS
+  constexpr int kAhead = G * kChunk;           // angles from one of the group's chunks to the next
+  // Records of the chunk two steps ahead (the group's first wave).
+  const bool rawwave = t < 64;   // uniform per wave
+  Raw<T> ahead;
+  // prologue: the ring entries of the first two chunks, the records of the
+  // third, then the first chunk's window straight into LDS
   {
     const int k0 = grp * kChunk;
-    if (t < kChunk && k0 + t < m) fill_meta<T>(meta[grp][0][t], a.ang[k0 + t], Xc, Yc, hb);
+    if (rawwave) {
+      Raw<T> r0, r1;
+      load_raw<T>(r0, a.ang, k0, t, m);
+      load_raw<T>(r1, a.ang, k0 + kAhead, t, m);
+      load_raw<T>(ahead, a.ang, k0 + 2 * kAhead, t, m);
+      fill_meta<T>(meta[grp][0], r0, k0, t, m, Xc, Yc, hb);
+      fill_meta<T>(meta[grp][1], r1, k0 + kAhead, t, m, Xc, Yc, hb);
+    }
     __syncthreads();
     Stage<T, MODE> sg;
-    stage_load<T, MODE>(sg, a, meta[grp][0], k0, t);
+    stage_load<T, MODE>(sg, a, meta[grp][0], grp * kChunk, t);
     stage_store<T, MODE>(sg, win[grp][0], alpha, t);
     __syncthreads();
   }
+  int mcur = 0;   // ring slot of the current chunk
   for (int st = 0; st < steps; ++st) {
+    set_priority(steps - 1 - st);   // chunk steps left
     const int cur = st & 1, nxt = cur ^ 1;
+    const int mnext = mcur == 2 ? 0 : mcur + 1, mfill = mnext == 2 ? 0 : mnext + 1;
     const int c = st * G + grp;                  // this group's chunk
     const int k0 = c * kChunk, kc = max(0, min(kChunk, m - k0));
-    const int k1 = k0 + G * kChunk;              // its next chunk
+    const int k1 = k0 + kAhead;                  // its next chunk
     const bool more = st + 1 < steps;
-    // stage the next chunk's constants, then start its window loads; they
-    // are consumed after the current chunk is done
-    if (more && t < kChunk && k1 + t < m) fill_meta<T>(meta[grp][nxt][t], a.ang[k1 + t], Xc, Yc, hb);
-    __syncthreads();
+    // start the next chunk's window loads; they are consumed after the
+    // current chunk is done
     Stage<T, MODE> pre;
-    if (more) stage_load<T, MODE>(pre, a, meta[grp][nxt], k1, t);
+    if (more) stage_load<T, MODE>(pre, a, meta[grp][mnext], k1, t);
     // compute the current chunk
+    const Meta<T>* __restrict__ mt = meta[grp][mcur];
 #pragma unroll 4
     for (int kk = 0; kk < kc; ++kk) {
-      const Meta<T> M = meta[grp][cur][kk];
+      const Meta<T> M = mt[kk];
       const T* w = win[grp][cur] + kk * kWin;
       const T Ja = fma(dX, M.c, fma(dY, M.s, M.base));
       const T Jb = fma(T(8), M.s, Ja);
       acc0 = pixel_term<T>(Ja, w, M, acc0);
       acc1 = pixel_term<T>(Jb, w, M, acc1);
     }
+    // ring entry of the chunk two steps ahead (its slot held the previous
+    // chunk, read before the last barrier), then the next window into LDS,
+    // then the records of the chunk three steps ahead
+    if (rawwave && k0 + 2 * kAhead < m)
+      fill_meta<T>(meta[grp][mfill], ahead, k0 + 2 * kAhead, t, m, Xc, Yc, hb);
     if (more) stage_store<T, MODE>(pre, win[grp][nxt], alpha, t);
+    if (rawwave && k0 + 3 * kAhead < m) load_raw<T>(ahead, a.ang, k0 + 3 * kAhead, t, m);
+    mcur = mnext;
     __syncthreads();
   }
+  set_priority(3);
   // CGLS: issue the epilogue's global loads before the partial-sum barrier
   T z_in[2] = {T(0), T(0)}, p_in[2] = {T(0), T(0)}, x_in[2] = {T(0), T(0)};
   double d_own = 0.0;   // d + lambda of the WMG pixel of threads < 256
@@ -291,11 +377,14 @@ __device__ __forceinline__ void backward_body(const BwdK<T>& a, const BlockPos p
   if constexpr (MODE == BWD_CGLS || MODE == BWD_CGLS_INIT) {
     // s = W^T r - lambda x for the tile's pixels, after p = z + beta p and
     // x += alpha p; then z = M^-1 s on the tile and the four dot products.
+    // With the WMG apply fused, p, x and z are stored after the block has
+    // taken its reduction ticket (whose wait covers the wave's pending stores).
     T* lds = &win[0][0][0] + G * 2 * kThreads;   // past the partial sums
     T (*stile)[kTile + 1] = reinterpret_cast<T (*)[kTile + 1]>(lds);
     T (*ptile)[kTile + 1] = reinterpret_cast<T (*)[kTile + 1]>(lds + kTile * (kTile + 1));
     const double lambda = a.st->lambda;
     const int x0 = pos.x * kTile, y0 = pos.y * kTile;
+    T pv_new[2] = {T(0), T(0)}, xn_new[2] = {T(0), T(0)};
     if (grp == 0) {
 #pragma unroll
       for (int q = 0; q < 2; ++q) {
@@ -306,14 +395,20 @@ __device__ __forceinline__ void backward_body(const BwdK<T>& a, const BlockPos p
           T xn;
           if constexpr (MODE == BWD_CGLS) {
             pv = (T)((double)z_in[q] + beta * (double)p_in[q]);
-            a.p[px] = pv;
             xn = (T)((double)x_in[q] + alpha * (double)pv);
-            a.xo[px] = xn;
           } else {
             xn = x_in[q];
           }
+          pv_new[q] = pv;
+          xn_new[q] = xn;
           sv = (T)(bp[q] - lambda * (double)xn);
-          if (!a.fuse) a.out[px] = sv;
+          if (!a.fuse) {
+            if constexpr (MODE == BWD_CGLS) {
+              a.p[px] = pv;
+              a.xo[px] = xn;
+            }
+            a.out[px] = sv;
+          }
         }
         stile[ly][tx] = sv;
         ptile[ly][tx] = pv;
@@ -339,11 +434,10 @@ __device__ __forceinline__ void backward_body(const BwdK<T>& a, const BlockPos p
       }
     }
     double v[4] = {0.0, 0.0, 0.0, 0.0};   // <s,z>, ||s||^2, ||z||^2, <z,p>
+    T z = T(0), zt = T(0);
     if (tt < kTile * kTile) {
-      const T z = stile[qy][qx];
-      if (x0 + qx < n && y0 + qy < n) a.zP[(size_t)(y0 + qy) * a.ld + x0 + qx + kPad] = z;
-      // transposed copy: consecutive threads write consecutive addresses
-      if (x0 + qy < n && y0 + qx < n) a.zTP[(size_t)(x0 + qy) * a.ld + y0 + qx + kPad] = stile[qx][qy];
+      z = stile[qy][qx];
+      zt = stile[qx][qy];
       const double sd = (double)s_own, zd = (double)z;
       v[0] = sd * zd;
       v[1] = sd * sd;
@@ -355,6 +449,23 @@ __device__ __forceinline__ void backward_body(const BwdK<T>& a, const BlockPos p
                                             [sst](double (&tot)[4]) {
                                               cgls_precond_finish(sst, tot, MODE == BWD_CGLS_INIT);
                                             });
+    if constexpr (MODE == BWD_CGLS) {
+      if (grp == 0) {
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+          if (ix < n && iys[q] < n) {
+            const size_t px = (size_t)iys[q] * n + ix;
+            a.p[px] = pv_new[q];
+            a.xo[px] = xn_new[q];
+          }
+        }
+      }
+    }
+    if (tt < kTile * kTile) {
+      if (x0 + qx < n && y0 + qy < n) a.zP[(size_t)(y0 + qy) * a.ld + x0 + qx + kPad] = z;
+      // transposed copy: consecutive threads write consecutive addresses
+      if (x0 + qy < n && y0 + qx < n) a.zTP[(size_t)(x0 + qy) * a.ld + y0 + qx + kPad] = zt;
+    }
     return;
   }
   if constexpr (MODE == BWD_SIRT) {

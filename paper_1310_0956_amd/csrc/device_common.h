@@ -43,13 +43,18 @@ __device__ __forceinline__ void block_sum(double (&v)[W], double* sh) {
   }
   __syncthreads();
   if (threadIdx.x == 0) {
+    // in wave order; two waves' values in flight at a time keeps the
+    // register count low
+    double t[W];
 #pragma unroll
-    for (int i = 0; i < W; ++i) {
-      double t = sh[i];
+    for (int i = 0; i < W; ++i) t[i] = sh[i];
+#pragma unroll 2
+    for (int w = 1; w < NW; ++w) {
 #pragma unroll
-      for (int w = 1; w < NW; ++w) t += sh[w * W + i];
-      v[i] = t;
+      for (int i = 0; i < W; ++i) t[i] += sh[w * W + i];
     }
+#pragma unroll
+    for (int i = 0; i < W; ++i) v[i] = t[i];
   }
   __syncthreads();
 }
@@ -60,15 +65,16 @@ __device__ __forceinline__ void block_sum256(double (&v)[W], double* sh) {
 }
 
 // Each block contributes W partial sums; the last block to arrive sums them in
-// block order and calls fin(totals) from thread 0.  Returns nothing; the
-// counter is reset for the next use.  Blocks have NW waves.
+// block order and calls fin(totals) from thread 0.  Returns normally in every
+// block; the counter is reset for the next use.  Blocks have NW waves.
 //
 // Visibility without a full L2 writeback: the partials are written with
 // agent-scope atomic stores, which write through to the device-coherent
 // level, and the block waits for their completion (vmcnt) before taking its
-// ticket; the last block reads them with agent-scope atomic loads.  Results
-// the finisher writes to the solver state are read by later launches (kernel
-// boundaries order them).
+// ticket; the last block reads them with agent-scope atomic loads.  The wait
+// covers every outstanding memory access of thread 0's wave, so callers issue
+// their bulk stores after this call.  Results the finisher writes to the
+// solver state are read by later launches (kernel boundaries order them).
 template <int W, int NW = 4, typename F>
 __device__ __forceinline__ void reduce_and_finish(double (&v)[W], const RedScratch& red,
                                                   int nblocks, int block_id, F fin) {
@@ -139,6 +145,19 @@ __device__ __forceinline__ void cgls_precond_finish(SolverState* st, const doubl
   else if (rr <= st->tol) st->done = 1;
   else if (st->iter >= st->max_iter) st->done = 2;
   else if (g == 0.0) st->done = 1;
+}
+
+// Wave issue priority 0..3 (higher issues first; equal priorities issue
+// oldest first).  Blocks that share a CU raise the priority of the ones with
+// more work left, so they finish together instead of leaving the last block
+// to run alone with too few waves to hide its latencies.
+__device__ __forceinline__ void set_priority(int p) {
+  switch (p) {
+    case 0: __builtin_amdgcn_s_setprio(0); break;
+    case 1: __builtin_amdgcn_s_setprio(1); break;
+    case 2: __builtin_amdgcn_s_setprio(2); break;
+    default: __builtin_amdgcn_s_setprio(3); break;
+  }
 }
 
 // Position of a block within its problem's grid.

@@ -352,22 +352,37 @@ __device__ __forceinline__ void forward_body(const FwdK<T>& a, const BlockPos bp
   const int rbytes = a.ld * (int)sizeof(T);
   Window wcur{0, 0};
   int cur_shift = 0;   // window start the walker's columns are currently relative to
+  // The window of band b + 1 is loaded during band b - 1 (two bands ahead of
+  // its first use), so no band waits on the table.  The load's index carries
+  // an opaque zero held in a vector register: the value then stays in vector
+  // registers until it is used, instead of being moved to scalar registers
+  // (which would wait for the load) right after it is issued.
+  int vzero;
+  asm volatile("v_mov_b32 %0, 0" : "=v"(vzero));
+  int2 wahead = make_int2(0, 0);
   if (nbands > 0) {
     const int2 w0 = bandwin[0];
+    if (nbands > 1) wahead = bandwin[1];
     wcur = Window{w0.x, w0.y};
     if (wcur.c1 - wcur.c0 + 1 <= kWinCols) {
+      // all of the band's loads are issued before the first LDS store
+      T v[STAGE_PER];
 #pragma unroll
       for (int i = 0; i < STAGE_PER; ++i) {
         const int row = srow + kStageRows * i;
-        T v = T(0);
+        v[i] = T(0);
         if (scol <= wcur.c1 - wcur.c0)
-          v = load_elem(rs, (unsigned)(wcur.c0 + kPad + scol) * sizeof(T), (lo + row) * rbytes, T(0));
-        if (stager) win[0][row * kStride + scol] = v;
+          v[i] = load_elem(rs, (unsigned)(wcur.c0 + kPad + scol) * sizeof(T), (lo + row) * rbytes,
+                           T(0));
       }
+#pragma unroll
+      for (int i = 0; i < STAGE_PER; ++i)
+        if (stager) win[0][(srow + kStageRows * i) * kStride + scol] = v[i];
     }
     __syncthreads();
   }
   for (int bnd = 0; bnd < nbands; ++bnd) {
+    set_priority((nbands - bnd) >> 2);   // bands left
     const int cur = bnd & 1, nxt = cur ^ 1;
     const int rb = lo + bnd * BAND;
     const int rows = min(BAND, hi - rb + 1);
@@ -377,7 +392,9 @@ __device__ __forceinline__ void forward_body(const FwdK<T>& a, const BlockPos bp
     bool next_lds = false;
     if (more) {
       const int rb2 = rb + BAND;
-      const int2 w1 = bandwin[bnd + 1];
+      const int2 w1 = make_int2(__builtin_amdgcn_readfirstlane(wahead.x),
+                                __builtin_amdgcn_readfirstlane(wahead.y));
+      if (bnd + 2 < nbands) wahead = bandwin[bnd + 2 + vzero];
       wnext = Window{w1.x, w1.y};
       next_lds = wnext.c1 - wnext.c0 + 1 <= kWinCols;
       if (next_lds) {
@@ -412,6 +429,7 @@ __device__ __forceinline__ void forward_body(const FwdK<T>& a, const BlockPos bp
     wcur = wnext;
     __syncthreads();
   }
+  set_priority(3);
   const T result = (T)a.h * fma(Wm, acc1, acc0);
   const size_t i = (size_t)k * nb + j;   // valid lanes only use it
   if constexpr (MODE == FWD_PLAIN) {
@@ -423,13 +441,13 @@ __device__ __forceinline__ void forward_body(const FwdK<T>& a, const BlockPos bp
     // of that iteration: this launch's last block overwrites it only after
     // every block has read it), then
     // q = W z + beta q_old  (q_old = W p_old, so q = W (z + beta p_old) = W p_new)
-    double q = 0.0;
+    // The new r and q are stored after the block has taken its reduction
+    // ticket (whose wait covers the wave's pending stores).
+    double q = 0.0, r_new = 0.0;
     if (valid) {
       const double q_old = (double)a.out[i];
-      a.r[i] = (T)((double)a.r[i] - alpha_prev * q_old);
-      q = (double)result + a.st->beta * q_old;
-      a.out[i] = (T)q;
-      q = (double)(T)q;
+      r_new = (double)a.r[i] - alpha_prev * q_old;
+      q = (double)(T)((double)result + a.st->beta * q_old);
     }
     double v[1] = {q * q};
     SolverState* st = a.st;
@@ -447,6 +465,10 @@ __device__ __forceinline__ void forward_body(const FwdK<T>& a, const BlockPos bp
                                             st->alpha = st->gamma / delta;
                                           }
                                         });
+    if (valid) {
+      a.r[i] = (T)r_new;
+      a.out[i] = (T)q;
+    }
   }
 }
 
