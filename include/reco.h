@@ -184,11 +184,18 @@ reco_status reco_solve_batch(int32_t count, const reco_geometry* geoms,
                              const reco_solve_opts* opts, reco_solve_info* info,
                              void* stream);
 
-/* Serving: a scheduler thread admits submitted requests while their Krylov
- * state fits in hbm_budget_bytes and fewer than max_slots run, and advances
- * all running requests together (continuous batching; one batched CGLS
- * iteration per tick, requests join and leave between ticks).  Geometries are
- * created on first use and cached by description. */
+/* Serving: submitted requests are admitted in arrival order while their
+ * geometry and Krylov state fit in hbm_budget_bytes and fewer than max_slots
+ * run.  Requests are served in two tiers by the cost of one iteration
+ * (n^2 * n_angles below or at least 1024^2 * 512), each with a scheduler
+ * thread and a stream of its own: the small tier advances all its running
+ * requests together (continuous batching; one batched CGLS iteration per
+ * tick, requests join and leave between ticks), the large tier runs one
+ * request at a time.  Geometries are created on first use (large ones on a
+ * builder thread and stream of their own) and cached by description; the
+ * server uses three streams.  Each result equals what reco_solve_cgls
+ * computes for the request alone.  ENOMEM from reco_poll: the request alone
+ * needs more than the budget. */
 reco_status reco_server_create(size_t hbm_budget_bytes, int32_t max_slots,
                                reco_server* out);
 

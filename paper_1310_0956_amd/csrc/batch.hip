@@ -15,6 +15,7 @@
 // host gathers the problems' done flags (one small kernel and one copy);
 // finished problems leave the work lists, new ones join (continuous
 // batching: the server below admits requests between ticks).
+#include <algorithm>
 #include <condition_variable>
 #include <deque>
 #include <map>
@@ -108,16 +109,21 @@ struct Slot {
 
 class Engine {
  public:
-  Engine(hipStream_t st, int iters_per_tick, bool use_graph)
+  // own_stream: st is used by this engine only (its graphs are captured on
+  // it); otherwise a capture stream of its own is created.  Every stream a
+  // process uses beyond the device's hardware queues shares a queue with
+  // another and then waits behind that stream's work.
+  Engine(hipStream_t st, int iters_per_tick, bool use_graph, bool own_stream = false)
       : st_(st), iters_(iters_per_tick), use_graph_(use_graph) {
-    HIP_CHECK(hipStreamCreateWithFlags(&cap_, hipStreamNonBlocking));
+    if (own_stream) cap_ = st_;
+    else HIP_CHECK(hipStreamCreateWithFlags(&cap_, hipStreamNonBlocking));
   }
   ~Engine() {
     drop_graph();
     if (d_sts_) (void)hipFree(d_sts_);
     if (d_flags_) (void)hipFree(d_flags_);
     if (h_flags_) (void)hipHostFree(h_flags_);
-    if (cap_) (void)hipStreamDestroy(cap_);
+    if (cap_ && cap_ != st_) (void)hipStreamDestroy(cap_);
   }
   Engine(const Engine&) = delete;
   Engine& operator=(const Engine&) = delete;
@@ -410,10 +416,11 @@ reco_status solve_batch(int32_t count, const reco_geometry* geoms, const void* c
 // ---------------------------------------------------------------------------
 // Server: continuous batching with admission by device-memory budget
 // ---------------------------------------------------------------------------
-// Threads: the caller's (submit / poll), the scheduler (admission, ticks of
-// the batched engine on the server's stream) and a geometry builder (tables
-// and packet diagonal of descriptions seen for the first time, on a stream
-// of its own, so that running requests keep advancing meanwhile).
+// Threads: the caller's (submit / poll), a scheduler per cost tier
+// (admission, ticks of the tier's batched engine on its own stream) and a
+// geometry builder for the large tier (tables and packet diagonal of
+// descriptions seen for the first time, on a stream of its own, so that
+// running requests keep advancing meanwhile).
 namespace {
 
 struct Request {
@@ -451,6 +458,25 @@ DescKey key_of(const reco_geometry_desc& d) {
 
 }  // namespace
 
+// Requests are split into two tiers by the cost of one iteration, each with
+// its own scheduler thread, batched engine and stream: the GPU interleaves
+// the streams, so a small problem is not held to one iteration per tick of a
+// batch that also advances 2048^2 problems.  The large tier runs one problem
+// at a time (in admission order), each at the speed of a solo solve, and
+// builds new geometries (up to ~150 ms of GPU work) on a builder thread and
+// stream of their own; the small tier batches all of its admitted problems
+// and builds its geometries (about a millisecond each) itself between ticks.
+// Three streams in all, so that each keeps a hardware queue to itself.
+// Admission (arrival order, slot and memory accounting) is shared.
+constexpr int kTiers = 2;
+constexpr int kTierRunning[kTiers] = {1 << 30, 1};   // problems a tier advances at once
+constexpr bool kTierBuilder[kTiers] = {false, true};  // geometries built on a thread of their own
+
+int tier_of(const reco_geometry_desc& d) {
+  const double cost = (double)d.n * d.n * d.n_angles;   // ~ updates per iteration
+  return cost >= 1024.0 * 1024.0 * 512.0 ? 1 : 0;
+}
+
 struct Server {
   size_t budget = 0;
   int max_slots = 0;
@@ -460,20 +486,27 @@ struct Server {
   std::deque<Request*> queue;
   std::unordered_map<uint64_t, std::unique_ptr<Request>> all;
   uint64_t next_ticket = 1;
-  uint64_t submits = 0, builds = 0;   // change counters the scheduler waits on
+  // change counters the schedulers wait on: submissions, finished builds,
+  // requests that left a tier (freeing slots and memory)
+  uint64_t submits = 0, builds = 0, retires = 0;
   bool stop = false, stop_builder = false;
-  std::thread th, builder;
+  std::string fatal;                  // a scheduler could not start: every request fails
+  std::thread th[kTiers], builder[kTiers];   // builder[t] runs only if kTierBuilder[t]
   std::map<DescKey, GeoEntry> geos;
-  std::deque<DescKey> to_build;
+  std::deque<DescKey> to_build[kTiers];
   std::vector<Request*> waiting;      // admitted, geometry not built yet
   size_t used = 0;                    // geometries + workspaces held
   int running = 0;                    // admitted requests
 
-  void run();
-  void build_loop();
+  void run(int tier);
+  void build_loop(int tier);
+  void build_one(const DescKey& k, const reco_geometry_desc& d, hipStream_t st,
+                 const std::string& err_stream);
+  void admit();
   void finish(Request* r, reco_status st, const std::string& err);
   void release(Request* r);
   bool make_room(size_t need);
+  void stop_threads();
 };
 
 static double seconds_now() { return now_ms() * 1e-3; }
@@ -526,143 +559,196 @@ bool Server::make_room(size_t need) {
   return used + need <= budget;
 }
 
-void Server::build_loop() {
+// Admit queued requests in arrival order while slots and memory allow; a
+// request whose geometry is new queues its build with its tier's builder.
+// Lock held.
+void Server::admit() {
+  bool new_builds = false;
+  while (!queue.empty() && running < max_slots) {
+    Request* r = queue.front();
+    const DescKey k = key_of(r->desc);
+    auto need_of = [&]() {
+      auto it = geos.find(k);
+      if (it == geos.end()) return geometry_bytes(r->desc) + cgls_workspace_bytes(r->desc);
+      const GeoEntry& e = it->second;
+      return e.workspaces - e.running > 0 ? (size_t)0 : e.ws_bytes;
+    };
+    size_t need = need_of();
+    if (need > budget) {
+      queue.pop_front();
+      finish(r, RECO_ENOMEM, "request needs " + std::to_string(need) +
+                                 " device bytes, more than the server budget");
+      continue;
+    }
+    if (used + need > budget) {
+      make_room(need);
+      need = need_of();   // eviction may have dropped its geometry
+      if (used + need > budget) break;
+    }
+    queue.pop_front();
+    GeoEntry& e = geos[k];
+    if (e.ws_bytes == 0) {
+      e.desc = r->desc;
+      e.bytes = geometry_bytes(r->desc);
+      e.ws_bytes = cgls_workspace_bytes(r->desc);
+    }
+    if (!e.g && !e.building) {
+      e.building = true;
+      e.err = RECO_OK;
+      to_build[tier_of(r->desc)].push_back(k);
+      new_builds = true;
+    }
+    r->fresh_ws = e.workspaces - e.running <= 0;
+    if (r->fresh_ws) ++e.workspaces;
+    ++e.running;
+    r->need = need;
+    used += need;
+    ++running;
+    waiting.push_back(r);
+  }
+  if (new_builds) cv.notify_all();
+}
+
+void Server::build_loop(int tier) {
   (void)hipSetDevice(device);
   hipStream_t st = nullptr;
-  std::string fatal;
+  std::string err_stream;
   if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
     (void)hipGetLastError();
-    fatal = "could not create the geometry builder's stream";
+    err_stream = "could not create a geometry builder's stream";
   }
   for (;;) {
     reco_geometry_desc d{};
     DescKey k;
     {
       std::unique_lock<std::mutex> lk(mu);
-      cv.wait(lk, [&] { return stop_builder || !to_build.empty(); });
-      if (to_build.empty()) break;
-      k = to_build.front();
-      to_build.pop_front();
+      cv.wait(lk, [&] { return stop_builder || !to_build[tier].empty(); });
+      if (to_build[tier].empty()) break;
+      k = to_build[tier].front();
+      to_build[tier].pop_front();
       d = geos[k].desc;
     }
-    Geometry* g = nullptr;
-    reco_status err = RECO_OK;
-    std::string msg;
-    if (!fatal.empty()) {
-      err = RECO_EDEVICE;
-      msg = fatal;
-    } else {
-      try {
-        g = create_geometry(d, st);
-      } catch (const Error& e) {
-        err = e.code;
-        msg = e.msg;
-      }
-    }
-    {
-      std::lock_guard<std::mutex> lk(mu);
-      GeoEntry& e = geos[k];
-      e.building = false;
-      e.g = g;
-      e.err = err;
-      e.err_msg = msg;
-      ++builds;
-    }
-    cv.notify_all();
+    build_one(k, d, st, err_stream);
   }
   if (st) (void)hipStreamDestroy(st);
 }
 
-void Server::run() {
+// Build one geometry and publish it (or its error).  Lock not held.
+void Server::build_one(const DescKey& k, const reco_geometry_desc& d, hipStream_t st,
+                       const std::string& err_stream) {
+  Geometry* g = nullptr;
+  reco_status err = RECO_OK;
+  std::string msg;
+  if (!err_stream.empty()) {
+    err = RECO_EDEVICE;
+    msg = err_stream;
+  } else {
+    try {
+      g = create_geometry(d, st);
+    } catch (const Error& e) {
+      err = e.code;
+      msg = e.msg;
+    }
+  }
+  {
+    std::lock_guard<std::mutex> lk(mu);
+    GeoEntry& e = geos[k];
+    e.building = false;
+    e.g = g;
+    e.err = err;
+    e.err_msg = msg;
+    ++builds;
+  }
+  cv.notify_all();
+}
+
+void Server::run(int tier) {
   (void)hipSetDevice(device);
   hipStream_t st = nullptr;
-  std::string fatal;
   std::unique_ptr<Engine> eng;
   try {
     HIP_CHECK(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
-    eng.reset(new Engine(st, 1, true));
+    eng.reset(new Engine(st, 1, true, true));
   } catch (const Error& e) {
-    fatal = e.msg;
+    {
+      std::lock_guard<std::mutex> lk(mu);
+      if (fatal.empty()) fatal = e.msg;
+    }
+    cv.notify_all();
   }
   std::vector<Request*> active;
-  uint64_t seen_submits = ~0ull, seen_builds = ~0ull;
-  bool retired = false;   // the last tick freed slots or memory
+  uint64_t seen_submits = ~0ull, seen_builds = ~0ull, seen_retires = ~0ull;
   for (;;) {
     std::vector<Request*> ready;
     {
       std::unique_lock<std::mutex> lk(mu);
       if (!fatal.empty()) {
+        // no request can be served: fail what is queued or waiting
         for (Request* r : queue) finish(r, RECO_EDEVICE, fatal);
         queue.clear();
-        if (stop) break;
-        cv.wait(lk, [&] { return stop || !queue.empty(); });
-        continue;
-      }
-      const bool changed = retired || seen_submits != submits || seen_builds != builds;
-      seen_submits = submits;
-      seen_builds = builds;
-      retired = false;
-      if (active.empty() && !changed) {
-        if (stop && queue.empty() && waiting.empty()) break;
-        cv.wait(lk, [&] { return stop || submits != seen_submits || builds != seen_builds; });
-        continue;
-      }
-      // admit in arrival order while slots and memory allow
-      bool new_builds = false;
-      while (!queue.empty() && running < max_slots) {
-        Request* r = queue.front();
-        const DescKey k = key_of(r->desc);
-        auto need_of = [&]() {
-          auto it = geos.find(k);
-          if (it == geos.end()) return geometry_bytes(r->desc) + cgls_workspace_bytes(r->desc);
-          const GeoEntry& e = it->second;
-          return e.workspaces - e.running > 0 ? (size_t)0 : e.ws_bytes;
-        };
-        size_t need = need_of();
-        if (need > budget) {
-          queue.pop_front();
-          finish(r, RECO_ENOMEM, "request needs " + std::to_string(need) +
-                                     " device bytes, more than the server budget");
+        for (Request* r : waiting) {
+          release(r);
+          finish(r, RECO_EDEVICE, fatal);
+        }
+        waiting.clear();
+        if (active.empty()) {
+          if (stop) break;
+          cv.wait(lk, [&] { return stop || !queue.empty(); });
           continue;
         }
-        if (used + need > budget) {
-          make_room(need);
-          need = need_of();   // eviction may have dropped its geometry
-          if (used + need > budget) break;
-        }
-        queue.pop_front();
-        GeoEntry& e = geos[k];
-        if (e.ws_bytes == 0) {
-          e.desc = r->desc;
-          e.bytes = geometry_bytes(r->desc);
-          e.ws_bytes = cgls_workspace_bytes(r->desc);
-        }
-        if (!e.g && !e.building) {
-          e.building = true;
-          e.err = RECO_OK;
-          to_build.push_back(k);
-          new_builds = true;
-        }
-        r->fresh_ws = e.workspaces - e.running <= 0;
-        if (r->fresh_ws) ++e.workspaces;
-        ++e.running;
-        r->need = need;
-        used += need;
-        ++running;
-        waiting.push_back(r);
       }
-      if (new_builds) cv.notify_all();
-      // requests whose geometry is ready (or failed) leave the waiting list
+      const bool changed =
+          seen_submits != submits || seen_builds != builds || seen_retires != retires;
+      seen_submits = submits;
+      seen_builds = builds;
+      seen_retires = retires;
+      if (active.empty() && !changed) {
+        const bool mine_waiting = std::any_of(waiting.begin(), waiting.end(), [&](Request* r) {
+          return tier_of(r->desc) == tier;
+        });
+        if (stop && queue.empty() && !mine_waiting) break;
+        cv.wait(lk, [&] {
+          return stop || submits != seen_submits || builds != seen_builds ||
+                 retires != seen_retires || !fatal.empty();
+        });
+        continue;
+      }
+      if (fatal.empty()) admit();
+      if (!kTierBuilder[tier]) {
+        // this tier builds its new geometries itself, on its own stream
+        std::vector<std::pair<DescKey, reco_geometry_desc>> todo;
+        for (const DescKey& k : to_build[tier]) todo.emplace_back(k, geos[k].desc);
+        to_build[tier].clear();
+        if (!todo.empty()) {
+          lk.unlock();
+          for (const auto& kd : todo) build_one(kd.first, kd.second, st, "");
+          lk.lock();
+        }
+      }
+      // this tier's requests whose geometry is ready (or failed) leave the
+      // waiting list, up to the tier's running limit, in admission order
       std::vector<Request*> still;
+      size_t room = (size_t)kTierRunning[tier] > active.size()
+                        ? (size_t)kTierRunning[tier] - active.size() : 0;
       for (Request* r : waiting) {
+        if (tier_of(r->desc) != tier) {
+          still.push_back(r);
+          continue;
+        }
         GeoEntry& e = geos[key_of(r->desc)];
         if (e.g) {
+          if (room == 0) {
+            still.push_back(r);
+            continue;
+          }
+          --room;
           ready.push_back(r);
         } else if (!e.building) {
           const reco_status code = e.err != RECO_OK ? e.err : RECO_EDEVICE;
           const std::string msg = e.err_msg;
           release(r);
           finish(r, code, msg.empty() ? "geometry creation failed" : msg);
+          ++retires;
         } else {
           still.push_back(r);
         }
@@ -690,52 +776,75 @@ void Server::run() {
         slots.push_back(&r->slot);
         active.push_back(r);
       } catch (const Error& err) {
-        std::lock_guard<std::mutex> lk(mu);
-        release(r);
-        finish(r, err.code, err.msg);
+        {
+          std::lock_guard<std::mutex> lk(mu);
+          release(r);
+          finish(r, err.code, err.msg);
+          ++retires;
+        }
+        cv.notify_all();
       }
     }
     if (active.empty()) continue;
     try {
       eng->add(slots);
       std::vector<Slot*> done = eng->tick();
-      std::lock_guard<std::mutex> lk(mu);
-      retired = !done.empty();
-      for (Slot* s : done) {
-        Request* r = (Request*)s->owner;
-        GeoEntry& e = geos[key_of(r->desc)];
-        return_workspace(*e.g, s->w);
-        --e.running;
-        --running;
-        fill_info(*s, &r->info);
-        r->status = r->info.status;
-        r->t[2] = s->t_done * 1e-3;
-        if (s->failed) r->error = "solver state did not terminate on the device";
-        active.erase(std::find(active.begin(), active.end(), r));
+      if (!done.empty()) {
+        {
+          std::lock_guard<std::mutex> lk(mu);
+          for (Slot* s : done) {
+            Request* r = (Request*)s->owner;
+            GeoEntry& e = geos[key_of(r->desc)];
+            return_workspace(*e.g, s->w);
+            --e.running;
+            --running;
+            fill_info(*s, &r->info);
+            r->status = r->info.status;
+            r->t[2] = s->t_done * 1e-3;
+            if (s->failed) r->error = "solver state did not terminate on the device";
+            active.erase(std::find(active.begin(), active.end(), r));
+          }
+          ++retires;
+        }
+        cv.notify_all();
       }
     } catch (const Error& err) {
-      std::lock_guard<std::mutex> lk(mu);
-      fatal = err.msg;
-      for (Request* r : active) finish(r, RECO_EDEVICE, fatal);
-      for (Request* r : waiting) finish(r, RECO_EDEVICE, fatal);
-      active.clear();
-      waiting.clear();
+      {
+        std::lock_guard<std::mutex> lk(mu);
+        if (fatal.empty()) fatal = err.msg;
+        for (Request* r : active) finish(r, RECO_EDEVICE, err.msg);
+        active.clear();
+        ++retires;
+      }
+      cv.notify_all();
     }
   }
+  eng.reset();
+  if (st) (void)hipStreamDestroy(st);
+}
+
+// Stop and join the schedulers, then the builders, then free the geometries.
+void Server::stop_threads() {
+  {
+    std::lock_guard<std::mutex> lk(mu);
+    stop = true;
+  }
+  cv.notify_all();
+  for (auto& t : th)
+    if (t.joinable()) t.join();
   {
     std::lock_guard<std::mutex> lk(mu);
     stop_builder = true;
   }
   cv.notify_all();
-  if (builder.joinable()) builder.join();
-  eng.reset();
+  for (auto& t : builder)
+    if (t.joinable()) t.join();
   for (auto& kv : geos) {
     if (!kv.second.g) continue;
     release_workspaces(*kv.second.g);
     delete kv.second.g;
   }
   geos.clear();
-  if (st) (void)hipStreamDestroy(st);
 }
 
 }  // namespace reco
@@ -758,16 +867,13 @@ reco_status reco_server_create(size_t hbm_budget_bytes, int32_t max_slots, reco_
     s->max_slots = max_slots;
     reco::check_hip(hipGetDevice(&s->device), "hipGetDevice", __FILE__, __LINE__);
     reco::Server* p = s.get();
-    s->builder = std::thread([p] { p->build_loop(); });
     try {
-      s->th = std::thread([p] { p->run(); });
-    } catch (...) {
-      {
-        std::lock_guard<std::mutex> lk(p->mu);
-        p->stop_builder = true;
+      for (int t = 0; t < reco::kTiers; ++t) {
+        if (reco::kTierBuilder[t]) s->builder[t] = std::thread([p, t] { p->build_loop(t); });
+        s->th[t] = std::thread([p, t] { p->run(t); });
       }
-      p->cv.notify_all();
-      p->builder.join();
+    } catch (...) {
+      p->stop_threads();
       throw;
     }
     *out = reinterpret_cast<reco_server>(s.release());
@@ -784,12 +890,7 @@ reco_status reco_server_create(size_t hbm_budget_bytes, int32_t max_slots, reco_
 reco_status reco_server_destroy(reco_server h) {
   if (!h) return RECO_OK;
   reco::Server* s = reinterpret_cast<reco::Server*>(h);
-  {
-    std::lock_guard<std::mutex> lk(s->mu);
-    s->stop = true;
-  }
-  s->cv.notify_all();
-  if (s->th.joinable()) s->th.join();
+  s->stop_threads();
   delete s;
   return RECO_OK;
 }

@@ -16,6 +16,8 @@
 // tile, the tile's weights are Walsh-transformed by the lanes that hold the
 // tile (one row per lane); their squares are summed per angle and added to
 // float64 sums, in a fixed order (deterministic, no atomics).
+#include <algorithm>
+
 #include "device_common.h"
 #include "timing.h"
 
@@ -266,9 +268,14 @@ __device__ __forceinline__ void y_stages(T (&w)[1 << L], const T (&sgn)[L > 0 ? 
 // fixed order (deterministic, no atomics).
 // The butterflies keep the low element as u + v and the high one as u - v, so
 // the coefficients land in the in-place layout of the apply.
+// One launch covers angles [k0, k1): the running float64 sums are kept in d64
+// between launches (first: start from zero), and the last launch scales them
+// and writes both copies.  The angle order, hence the result, does not depend
+// on how the angles are split over launches.
 template <typename T, int L>
 __global__ __launch_bounds__(256) void k_packet_diag(const BwdAngle* __restrict__ ang, double* d64,
-                                                     T* dT, int n, int m, int nb, double h) {
+                                                     T* dT, int n, int nb, double h, int k0,
+                                                     int k1, int first, int last) {
   constexpr int Tt = 1 << L;
   constexpr int TPW = 64 / Tt;   // tiles per wave
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -287,9 +294,10 @@ __global__ __launch_bounds__(256) void k_packet_diag(const BwdAngle* __restrict_
   for (int b = 0; b < L; ++b) sgn[b] = ((y >> b) & 1) ? T(-1) : T(1);
   double acc[Tt];
 #pragma unroll
-  for (int x = 0; x < Tt; ++x) acc[x] = 0.0;
+  for (int x = 0; x < Tt; ++x)
+    acc[x] = (first || !active) ? 0.0 : d64[(size_t)(tyT * Tt + y) * n + txT * Tt + x];
 
-  for (int k = 0; k < m; ++k) {
+  for (int k = k0; k < k1; ++k) {
     const BwdAngle A = ang[k];
     const double Jt = fma(Xt, A.c, fma(Yt, A.s, hb));
     const double jbase = floor(Jt);
@@ -341,22 +349,37 @@ __global__ __launch_bounds__(256) void k_packet_diag(const BwdAngle* __restrict_
 #pragma unroll
     for (int x = 0; x < Tt; ++x) {
       const int ix = txT * Tt + x;
-      const double v = acc[x] * scale;
-      d64[(size_t)iy * n + ix] = v;
-      dT[(size_t)iy * n + ix] = (T)v;
+      if (last) {
+        const double v = acc[x] * scale;
+        d64[(size_t)iy * n + ix] = v;
+        dT[(size_t)iy * n + ix] = (T)v;
+      } else {
+        d64[(size_t)iy * n + ix] = acc[x];
+      }
     }
   }
 }
 
+// The angles are split over launches of about a millisecond each: every block
+// of a launch stays resident for the whole launch, so kernels of other
+// streams (the solves of a server) get the CUs between launches.
 template <typename T, int L>
 void diag_launch_L(Geometry& g, hipStream_t st) {
   const int ntiles = (g.n >> L) * (g.n >> L);
   const int tiles_per_block = 4 * (64 >> L);
   const int blocks = (ntiles + tiles_per_block - 1) / tiles_per_block;
-  TimedLaunch tl(TK_PACKET_DIAG, st);
-  hipLaunchKernelGGL((k_packet_diag<T, L>), dim3(blocks), dim3(256), 0, st, g.d_bwd, g.d_diag64,
-                     (T*)g.d_diag, g.n, g.m, g.nb, g.h);
-  HIP_CHECK(hipGetLastError());
+  // butterfly work of one angle: tiles x bins reaching a tile x 4^L * 2L;
+  // about 1.5e13 of these per second (measured at 2048^2, 2^L = 16)
+  const double Tt = (double)(1 << L);
+  const double per_angle = (double)ntiles * (1.2 * Tt + 3.0) * Tt * Tt * (2.0 * L + 1.0);
+  const int per_launch = (int)std::max(1.0, std::min((double)g.m, 1.5e10 / per_angle));
+  for (int k0 = 0; k0 < g.m; k0 += per_launch) {
+    const int k1 = std::min(g.m, k0 + per_launch);
+    TimedLaunch tl(TK_PACKET_DIAG, st);
+    hipLaunchKernelGGL((k_packet_diag<T, L>), dim3(blocks), dim3(256), 0, st, g.d_bwd, g.d_diag64,
+                       (T*)g.d_diag, g.n, g.nb, g.h, k0, k1, k0 == 0 ? 1 : 0, k1 == g.m ? 1 : 0);
+    HIP_CHECK(hipGetLastError());
+  }
 }
 
 template <typename T>

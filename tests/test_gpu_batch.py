@@ -176,6 +176,34 @@ def test_server_results_equal_solo():
         assert np.array_equal(xs[i].cpu().numpy(), xr), i
 
 
+def test_server_tiers_mixed_sizes():
+    """Requests whose iteration costs at least that of a 1024^2 image with
+    512 angles run in the server's large tier (one at a time, geometry built
+    on its own thread); the others are batched in the small tier.  Results
+    equal solo solves in both tiers."""
+    print_case("server tiers")
+    reqs = [(1024, 512, 1449, 4, 1e-2), (128, 90, 182, 2, 1e-3), (1024, 512, 1449, 4, 1e-3),
+            (256, 180, 363, 2, 1e-3), (64, 90, 91, 2, 1e-2)]
+    srv = reco.Server(8 << 30, max_slots=16)
+    try:
+        gs = _geoms([r[:4] for r in reqs])
+        bs = [_data(g, 6 + i, 7500 + i) for i, g in enumerate(gs)]
+        xs = [g.new_image() for g in gs]
+        tickets = [srv.submit(n, m, nb, lv, b, x, tol=tol)
+                   for (n, m, nb, lv, tol), b, x in zip(reqs, bs, xs)]
+        res = _wait(srv, tickets)
+    finally:
+        srv.close()
+    for i, (g, t) in enumerate(zip(gs, tickets)):
+        r = res[t]
+        assert r["status"] == "ok", r
+        xr, ir = _solo(g, bs[i], tol=reqs[i][4])
+        assert r["iters"] == ir["iters"]
+        assert np.array_equal(xs[i].cpu().numpy(), xr), i
+    large = sorted((res[tickets[i]]["t_admit"], res[tickets[i]]["t_done"]) for i in (0, 2))
+    assert large[1][0] >= large[0][1] - 1e-6     # the large tier runs one problem at a time
+
+
 def test_server_one_slot_serialises():
     print_case("server one slot")
     gs, bs, xs, res = _server_run(8 << 30, 1, 0.0)
