@@ -85,6 +85,7 @@ struct Geometry {
   int ngroups = 0;
   void* d_fwd_rows = nullptr;  // [ngroups * bin blocks] row range of each forward block
   void* d_fwd_wins = nullptr;  // [ngroups * bin blocks][fwd_maxb] band column windows
+  int* d_fwd_order = nullptr;  // [ngroups * bin blocks] forward block run at each grid position
   int fwd_maxb = 0;
   BwdAngle* d_bwd = nullptr;   // [m]
   std::vector<FwdAngle> h_fwd;

@@ -24,6 +24,9 @@
 // Positions are walked in 32.32 fixed point (float path) or recomputed in
 // float64 (double path), so the geometry error stays far below the float
 // weight error.
+#include <algorithm>
+#include <vector>
+
 #include "device_common.h"
 #include "timing.h"
 
@@ -57,6 +60,7 @@ struct FwdK {
   const int* groups;   // [ngroups][8] angle indices, -1 = empty slot
   const int2* rows;    // [ngroups * nbx] row range of each block
   const int2* wins;    // [ngroups * nbx][maxb] column window of each band
+  const int* order;    // [ngroups * nbx] block (g * nbx + bin block) run at each grid position
   int nbx, maxb;
   SolverState* st;
   RedScratch red;
@@ -314,8 +318,9 @@ __device__ __forceinline__ void forward_body(const FwdK<T>& a, const BlockPos bp
   __shared__ T win[2][BAND * kStride];
   const int t = threadIdx.x;
   const int n = a.n, nb = a.nb;
-  const int g = bp.y;
-  const int jfirst = bp.x * kBins;
+  const int lb = a.order[bp.id()];   // block run at this grid position
+  const int g = lb / a.nbx, bx = lb - g * a.nbx;
+  const int jfirst = bx * kBins;
   const int jlast = min(jfirst + kBins - 1, nb - 1);
   const int k0 = a.groups[g * kSlots];            // first angle: sets the walk axis
   // ray of this thread: a wave holds two angles of the group, interleaved by
@@ -333,7 +338,7 @@ __device__ __forceinline__ void forward_body(const FwdK<T>& a, const BlockPos bp
   const __amdgpu_buffer_rsrc_t rs = image_rsrc(img, (size_t)n * a.ld * sizeof(T));
   const double P0 = fma((double)j, ang.inv, ang.A0);
   // rows the block's rays touch and the column window of each band (setup table)
-  const int blk = g * a.nbx + bp.x;
+  const int blk = lb;
   const int2 rr = a.rows[blk];
   const int lo = rr.x, hi = rr.y;
   const int2* __restrict__ bandwin = a.wins + (size_t)blk * a.maxb;
@@ -564,6 +569,7 @@ FwdK<T> make_args(const Geometry& g, const FwdArgs& a) {
   k.groups = g.d_groups;
   k.rows = (const int2*)g.d_fwd_rows;
   k.wins = (const int2*)g.d_fwd_wins;
+  k.order = g.d_fwd_order;
   k.nbx = (g.nb + kBins - 1) / kBins;
   k.maxb = g.fwd_maxb;
   k.st = a.st;
@@ -607,11 +613,40 @@ void build_forward_windows(Geometry& g, hipStream_t st) {
   const size_t nblk = (size_t)g.ngroups * nbx;
   HIP_CHECK(hipMalloc(&g.d_fwd_rows, sizeof(int2) * nblk));
   HIP_CHECK(hipMalloc(&g.d_fwd_wins, sizeof(int2) * nblk * g.fwd_maxb));
+  HIP_CHECK(hipMalloc(&g.d_fwd_order, sizeof(int) * nblk));
   const long long total = (long long)nblk * (g.fwd_maxb + 1);
   hipLaunchKernelGGL(k_fwd_windows, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st,
                      g.d_fwd, g.d_groups, g.ngroups, nbx, g.n, g.nb, band, g.fwd_maxb,
                      (int2*)g.d_fwd_rows, (int2*)g.d_fwd_wins);
   HIP_CHECK(hipGetLastError());
+  // Grid order: blocks walk from 1 to n rows depending on how far their bins
+  // are from the detector centre.  Sorted by rows (most first) and dealt out
+  // in rounds of one block per CU, alternating direction, every run of
+  // consecutive grid positions of one CU count holds a similar amount of
+  // work; blocks are dispatched in grid order.
+  std::vector<int2> rows(nblk);
+  HIP_CHECK(hipMemcpyAsync(rows.data(), g.d_fwd_rows, sizeof(int2) * nblk, hipMemcpyDeviceToHost,
+                           st));
+  HIP_CHECK(hipStreamSynchronize(st));
+  std::vector<int> byrows(nblk);
+  for (size_t i = 0; i < nblk; ++i) byrows[i] = (int)i;
+  std::stable_sort(byrows.begin(), byrows.end(), [&](int a, int b) {
+    return rows[a].y - rows[a].x > rows[b].y - rows[b].x;
+  });
+  int cus = 0;
+  HIP_CHECK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, g.device));
+  const size_t P = (size_t)std::max(cus, 1);
+  std::vector<int> order(nblk);
+  for (size_t r = 0; r < nblk; ++r) {
+    const size_t round = r / P, c = r % P;
+    const size_t base = round * P;
+    const size_t width = std::min(P, nblk - base);
+    const size_t pos = base + ((round & 1) ? width - 1 - std::min(c, width - 1) : c);
+    order[pos] = byrows[r];
+  }
+  HIP_CHECK(hipMemcpyAsync(g.d_fwd_order, order.data(), sizeof(int) * nblk, hipMemcpyHostToDevice,
+                           st));
+  HIP_CHECK(hipStreamSynchronize(st));
 }
 
 int forward_blocks(const Geometry& g) { return ((g.nb + kBins - 1) / kBins) * g.ngroups; }
