@@ -48,11 +48,12 @@ def parse():
                     help="reconstructions in the batched leg (0: skip)")
     ap.add_argument("--serve", type=int, default=120,
                     help="requests in the serving leg (0: skip)")
-    ap.add_argument("--serve-rate", type=float, default=20.0, help="arrivals per second")
+    ap.add_argument("--serve-fracs", default="0.5,0.7,0.9",
+                    help="arrival rates as fractions of the one-at-a-time saturation throughput")
     ap.add_argument("--serve-budget-gib", type=float, default=64.0)
+    ap.add_argument("--serve-low-budget-gib", type=float, default=1.0,
+                    help="budget of one more run at 0.7 of saturation (0: skip)")
     ap.add_argument("--serve-slots", type=int, default=64)
-    ap.add_argument("--serve-extra", type=int, default=1,
-                    help="also serve at 35/s and with a 1 GiB budget (0: skip)")
     ap.add_argument("--no-tiny64", action="store_true", help="skip the 64^2 float64 leg")
     ap.add_argument("--no-ct2048", action="store_true", help="skip the 2048^2 leg")
     ap.add_argument("--no-solvers", action="store_true",
@@ -103,7 +104,8 @@ def traffic_for(family):
 def cpu_baseline(args):
     """Oracle WMG-CGLS on the host: whole reconstructions of the same workload,
     repeated until about ten seconds of CPU time (matrix assembly and packet
-    diagonal are setup, as on the GPU)."""
+    diagonal are setup, as on the GPU).  Returns the matrix too (for the
+    matvec timing)."""
     import numpy as np
     import inputs
     from oracle import solvers, wmg
@@ -126,7 +128,72 @@ def cpu_baseline(args):
         t_sum += time.perf_counter() - t0
         iters.append(res.iters)
         solved += 1
-    return solved, t_sum, iters
+    return solved, t_sum, iters, W
+
+
+def cpu_matvec(W, threads):
+    """Oracle A and A^T (scipy CSR, float64; A^T stored as its own CSR matrix)
+    at the 512^2 workload: updates per second on one thread and on a pool of
+    threads over row blocks (scipy's CSR product releases the GIL)."""
+    import numpy as np
+    from concurrent.futures import ThreadPoolExecutor
+    WT = W.T.tocsr()
+    x = np.ones(W.shape[1])
+    y = np.ones(W.shape[0])
+    out = {"nnz": int(W.nnz), "threads": threads}
+
+    def rate(fn, reps=3):
+        fn()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        return W.nnz * reps / (time.perf_counter() - t0)
+
+    out["A_updates_per_s_1thread"] = round(rate(lambda: W @ x) / 1e6, 2)
+    out["AT_updates_per_s_1thread"] = round(rate(lambda: WT @ y) / 1e6, 2)
+    ex = ThreadPoolExecutor(threads)
+    for name, M, v in (("A", W, x), ("AT", WT, y)):
+        cuts = np.linspace(0, M.shape[0], threads + 1).astype(int)
+        blocks = [M[cuts[i]:cuts[i + 1]] for i in range(threads)]
+        out[f"{name}_updates_per_s_{threads}threads"] = round(
+            rate(lambda: list(ex.map(lambda B: B @ v, blocks))) / 1e6, 2)
+    ex.shutdown()
+    out["unit"] = "M updates/s"
+    return out
+
+
+def cpu_config0():
+    """The 64^2 float64 case on the oracle: 50 iterations each of SIRT, CGLS,
+    WMG-CGLS with the packet diagonal (the GPU method) and with exact packet
+    blocks (the additive-exact variant); relative residual and error against
+    the phantom."""
+    import numpy as np
+    import inputs
+    from oracle import solvers, wmg
+    from oracle.geometry import Geometry as OG
+    from oracle.projector import system_matrix
+    n, m, nb, L = 64, 90, 64, 1
+    W = system_matrix(OG(n, m, nb))
+    x = inputs.ellipse_phantom(n, 10, 0).ravel()
+    b = W @ x
+    d = wmg.packet_diagonal_by_angles(OG(n, m, nb), L)
+    blocks = wmg.galerkin_blocks(W, n, L)
+    runs = [("sirt", lambda: solvers.sirt(W, b, fixed_iters=50)),
+            ("cgls", lambda: solvers.pcgls(W, b, fixed_iters=50)),
+            ("wmg_cgls_diag", lambda: solvers.pcgls(
+                W, b, fixed_iters=50, precond=lambda v: wmg.apply_additive_diag(v, d, L))),
+            ("wmg_cgls_additive_exact", lambda: solvers.pcgls(
+                W, b, fixed_iters=50, precond=lambda v: wmg.apply_additive_exact(v, blocks, n, L)))]
+    out = {"workload": "tiny64 on the float64 oracle (the tiny64_f64 object's case), "
+                       "50 iterations each"}
+    for name, fn in runs:
+        t0 = time.perf_counter()
+        res = fn()
+        ms = (time.perf_counter() - t0) * 1e3
+        err = float(np.linalg.norm(res.x - x) / np.linalg.norm(x))
+        out[name] = {"ms": round(ms, 1), "relres": float("%.4g" % res.relres),
+                     "rel_error_vs_phantom": round(err, 5)}
+    return out
 
 
 def percentiles(v):
@@ -207,12 +274,14 @@ def batch_leg(reco, torch, count):
     }
 
 
-def serve_leg(reco, torch, count, rate, budget_gib, slots):
-    """Poisson arrivals into the continuous-batching server; the same requests
-    solved one at a time on the same GPU give the solo baseline."""
-    import threading
+def serve_setup(reco, torch, count):
+    """The served requests (sizes and seeds of the serving mix; they do not
+    depend on the arrival rate), their data, and the one-at-a-time baseline:
+    each request solved alone in arrival order, the first request of a
+    geometry also paying for building it (tables and packet diagonal), as in
+    the server.  The saturation throughput is count / total solo time."""
     import inputs
-    mix = inputs.serving_mix(count, rate)
+    mix = inputs.serving_mix(count, 1.0)   # arrivals at 1/s; a rate r divides them by r
     geo = {}
     for r in mix:
         k = (r.side, r.n_angles)
@@ -222,9 +291,6 @@ def serve_leg(reco, torch, count, rate, budget_gib, slots):
     gs = [geo[(r.side, r.n_angles)] for r in mix]
     bs = [gpu_sinogram(torch, g, r.n_ellipses, r.seed, r.noise) for g, r in zip(gs, mix)]
     xs = [g.new_image() for g in gs]
-    # solo baseline: each request alone in arrival order; the first request of a
-    # geometry also pays for building it (tables and packet diagonal), as in
-    # the server
     solo_ms, built = [], set()
     for g, b, x, r in zip(gs, bs, xs, mix):
         torch.cuda.synchronize()
@@ -235,12 +301,23 @@ def serve_leg(reco, torch, count, rate, budget_gib, slots):
         g.solve_cgls(b, x=x, tol=r.tol)
         torch.cuda.synchronize()
         solo_ms.append((time.perf_counter() - s0) * 1e3)
-    # one-at-a-time FIFO server fed the same arrivals, from the measured solo times
+    return {"mix": mix, "gs": gs, "bs": bs, "xs": xs, "solo_ms": solo_ms,
+            "geometries": len(built), "saturation": count / (sum(solo_ms) * 1e-3)}
+
+
+def serve_run(reco, torch, S, rate, budget_gib, slots):
+    """Poisson arrivals at `rate` into the server; the one-at-a-time FIFO
+    server fed the same arrivals is computed from the measured solo times."""
+    import threading
+    import inputs
+    mix, gs, bs = S["mix"], S["gs"], S["bs"]
+    count = len(mix)
+    arrivals = [r.arrival_s / rate for r in mix]
     fifo_lat, free_at = [], 0.0
-    for r, ms in zip(mix, solo_ms):
-        start = max(free_at, r.arrival_s)
+    for a, ms in zip(arrivals, S["solo_ms"]):
+        start = max(free_at, a)
         free_at = start + ms * 1e-3
-        fifo_lat.append((free_at - r.arrival_s) * 1e3)
+        fifo_lat.append((free_at - a) * 1e3)
     srv = reco.Server(int(budget_gib * (1 << 30)), max_slots=slots)
     tickets = [None] * count
     outs = [g.new_image() for g in gs]
@@ -248,7 +325,7 @@ def serve_leg(reco, torch, count, rate, budget_gib, slots):
 
     def submitter():
         for i, r in enumerate(mix):
-            dt = t_start + r.arrival_s - reco.clock()
+            dt = t_start + arrivals[i] - reco.clock()
             if dt > 0:
                 time.sleep(dt)
             tickets[i] = srv.submit(r.side, r.n_angles, r.n_bins, inputs.default_levels(r.side),
@@ -266,22 +343,41 @@ def serve_leg(reco, torch, count, rate, budget_gib, slots):
     srv.close()
     lat = [(v["t_done"] - v["t_submit"]) * 1e3 for v in res]
     span = max(v["t_done"] for v in res) - min(v["t_submit"] for v in res)
-    same = all(torch.equal(a, b) for a, b in zip(outs, xs))
     return {
-        "workload": f"{count} requests, Poisson arrivals at {rate}/s, side 256/512/1024/2048 "
-                    "at 40/30/20/10%, angles side/2..1.5 side, tol 1e-2 or 1e-3, 1% noise",
+        "rate_per_s": round(rate, 3), "budget_gib": budget_gib,
         "recons_per_s": round(count / span, 3),
         "latency_ms_p50_p99": percentiles(lat),
         "queue_ms_p50_p99": percentiles([(v["t_admit"] - v["t_submit"]) * 1e3 for v in res]),
-        "all_ok": all(v["status"] == "ok" for v in res),
-        "results_equal_solo": bool(same),
         "solo_fifo_latency_ms_p50_p99": percentiles(fifo_lat),
-        "solo_recons_per_s_busy": round(count / (sum(solo_ms) * 1e-3), 3),
-        "budget_gib": budget_gib, "max_slots": slots,
-        "geometries_built": len(built),
-        "note": "solo FIFO latency: a one-at-a-time server fed the same arrivals, computed "
-                "from each request's measured solo service time (geometry build on first use "
-                "plus the solve)",
+        "all_ok": all(v["status"] == "ok" for v in res),
+        "results_equal_solo": bool(all(torch.equal(a, b) for a, b in zip(outs, S["xs"]))),
+    }
+
+
+def serve_leg(reco, torch, args):
+    """The serving mix at fractions of the one-at-a-time saturation throughput,
+    and once more under a small device-memory budget."""
+    S = serve_setup(reco, torch, args.serve)
+    sat = S["saturation"]
+    runs = []
+    for frac in [float(f) for f in args.serve_fracs.split(",") if f]:
+        r = serve_run(reco, torch, S, frac * sat, args.serve_budget_gib, args.serve_slots)
+        r["fraction_of_saturation"] = frac
+        runs.append(r)
+    if args.serve_low_budget_gib > 0:
+        r = serve_run(reco, torch, S, 0.7 * sat, args.serve_low_budget_gib, args.serve_slots)
+        r["fraction_of_saturation"] = 0.7
+        runs.append(r)
+    return {
+        "workload": f"{args.serve} requests, Poisson arrivals, side 256/512/1024/2048 at "
+                    "40/30/20/10%, angles side/2..1.5 side, tol 1e-2 or 1e-3, 1% noise",
+        "saturation_recons_per_s": round(sat, 3),
+        "geometries_built": S["geometries"],
+        "max_slots": args.serve_slots,
+        "runs": runs,
+        "note": "saturation: the one-at-a-time throughput (request count over the summed solo "
+                "service times, geometry build on first use plus the solve); solo FIFO "
+                "latency: a one-at-a-time server fed the same arrivals, from those service times",
     }
 
 
@@ -359,6 +455,21 @@ def ct2048_leg(reco, torch):
     kt = reco.timing_read()
     reco.timing_enable(False)
     it = sum(i["iters"] for i in infos)
+    # A and A^T alone: plain projections of the reconstruction and of the data
+    q = g.project(x)
+    bt = g.backproject(b)
+    torch.cuda.synchronize()
+    reco.timing_reset()
+    reco.timing_enable(True)
+    for _ in range(5):
+        g.project(x, out=q)
+    for _ in range(5):
+        g.backproject(b, out=bt)
+    torch.cuda.synchronize()
+    kt_alone = reco.timing_read()
+    reco.timing_enable(False)
+    a_ms = kt_alone["forward"][1] / kt_alone["forward"][0]
+    at_ms = kt_alone["backward"][1] / kt_alone["backward"][0]
     fwd = nnz * it / (kt["forward"][1] * 1e-3) / 1e9
     bwd = nnz * (it + reps) / (kt["backward"][1] * 1e-3) / 1e9
     return {
@@ -371,6 +482,12 @@ def ct2048_leg(reco, torch):
         "AT_frac_of_alu_peak": round(bwd / (PEAK_VALU_LANE_OPS / ALG_OPS_PER_UPDATE / 1e9), 4),
         # per launch that did work (launches issued after the device marked a
         # solve finished return at once and are not counted)
+        "A_alone": {"ms": round(a_ms, 4), "gupdates_per_s": round(nnz / (a_ms * 1e-3) / 1e9, 2),
+                    "frac_of_alu_peak": round(nnz / (a_ms * 1e-3) / 1e9
+                                              / (PEAK_VALU_LANE_OPS / ALG_OPS_PER_UPDATE / 1e9), 4)},
+        "AT_alone": {"ms": round(at_ms, 4), "gupdates_per_s": round(nnz / (at_ms * 1e-3) / 1e9, 2),
+                     "frac_of_alu_peak": round(nnz / (at_ms * 1e-3) / 1e9
+                                               / (PEAK_VALU_LANE_OPS / ALG_OPS_PER_UPDATE / 1e9), 4)},
         "kernel_avg_ms_working": {"forward": round(kt["forward"][1] / it, 4),
                                   "backward": round(kt["backward"][1] / (it + reps), 4)},
         "nnz": nnz, "setup_ms": round(setup_ms, 2),
@@ -511,15 +628,7 @@ def main():
     if args.batch > 0:
         result["batch"] = batch_leg(reco, torch, args.batch)
     if args.serve > 0:
-        result["serving"] = serve_leg(reco, torch, args.serve, args.serve_rate,
-                                      args.serve_budget_gib, args.serve_slots)
-        if args.serve_extra:
-            # a higher arrival rate, and a small device-memory budget that
-            # forces admission queueing
-            result["serving_rate35"] = serve_leg(reco, torch, args.serve, 35.0,
-                                                 args.serve_budget_gib, args.serve_slots)
-            result["serving_budget1g"] = serve_leg(reco, torch, args.serve, args.serve_rate,
-                                                   1.0, args.serve_slots)
+        result["serving"] = serve_leg(reco, torch, args)
     if not args.no_ct2048:
         result["ct2048"] = ct2048_leg(reco, torch)
     if not args.no_tiny64:
@@ -527,7 +636,10 @@ def main():
         torch.cuda.synchronize()
         result["tiny64_f64"] = tiny64_leg(reco, torch)
     if not args.no_cpu_baseline:
-        solved, t_sum, cpu_iters = cpu_baseline(args)
+        solved, t_sum, cpu_iters, W = cpu_baseline(args)
+        threads = min(16, os.cpu_count() or 1)
+        matvec = cpu_matvec(W, threads)
+        del W
         result["cpu_baseline"] = {
             "value": round(solved / t_sum, 5),
             "unit": "recons/s",
@@ -537,6 +649,8 @@ def main():
                       f"512^2 workload (scipy CSR matrix, single thread) to rel-res 1e-3 in "
                       f"{t_sum:.2f} s, {cpu_iters} iterations; matrix assembly and packet "
                       f"diagonal excluded as setup",
+            "matvec_ct512": matvec,
+            "tiny64_oracle": cpu_config0(),
         }
     print(json.dumps(result), flush=True)
 
