@@ -14,10 +14,49 @@ __device__ __forceinline__ T clamp01(T v, T hi) {
   return v < T(0) ? T(0) : (v > hi ? hi : v);
 }
 
+// Value of lane (lane ^ MASK) for MASK < 16, with DPP lane moves inside a row
+// of 16 lanes: xor 1 and 2 by quad permutes, 8 by a row rotation by 8, 4 by a
+// half-row mirror (i -> i ^ 7) followed by the quad permute i -> i ^ 3.
+// Larger masks use a general lane permute.
+template <int MASK>
+__device__ __forceinline__ int xor_lane_b32(int v) {
+  if constexpr (MASK == 1) return __builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, true);
+  else if constexpr (MASK == 2) return __builtin_amdgcn_mov_dpp(v, 0x4E, 0xF, 0xF, true);
+  else if constexpr (MASK == 4)
+    return __builtin_amdgcn_mov_dpp(__builtin_amdgcn_mov_dpp(v, 0x141, 0xF, 0xF, true), 0x1B, 0xF,
+                                    0xF, true);
+  else if constexpr (MASK == 8) return __builtin_amdgcn_mov_dpp(v, 0x128, 0xF, 0xF, true);
+  else return __shfl_xor(v, MASK, 64);
+}
+
+template <int MASK>
+__device__ __forceinline__ float xor_lane(float v) {
+  return __builtin_bit_cast(float, xor_lane_b32<MASK>(__builtin_bit_cast(int, v)));
+}
+template <int MASK>
+__device__ __forceinline__ double xor_lane(double v) {
+  const long long b = __builtin_bit_cast(long long, v);
+  const int lo = xor_lane_b32<MASK>((int)b), hi = xor_lane_b32<MASK>((int)(b >> 32));
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned)lo);
+}
+
+__device__ __forceinline__ double read_lane(double v, int lane) {
+  const long long b = __builtin_bit_cast(long long, v);
+  const int lo = __builtin_amdgcn_readlane((int)b, lane);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned)lo);
+}
+
+// Sum over the 64 lanes, the same value in every lane: butterflies within
+// each row of 16 lanes (DPP lane moves; every lane of a row ends with the
+// same row sum, each pairwise add being commutative), then the four row sums
+// in row order.  All lanes must be active.
 __device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
+  v += xor_lane<1>(v);
+  v += xor_lane<2>(v);
+  v += xor_lane<4>(v);
+  v += xor_lane<8>(v);
+  return (read_lane(v, 0) + read_lane(v, 16)) + (read_lane(v, 32) + read_lane(v, 48));
 }
 __device__ __forceinline__ int wave_min(int v) {
 #pragma unroll

@@ -222,32 +222,6 @@ void wmg_launch(const Geometry& g, WmgMode mode, const WmgArgs& a, hipStream_t s
   }
 }
 
-// Value of lane (lane ^ MASK) for MASK < 16, with DPP lane moves inside a row
-// of 16 lanes: xor 1 and 2 by quad permutes, 8 by a row rotation by 8, 4 by a
-// half-row mirror (i -> i ^ 7) followed by the quad permute i -> i ^ 3.
-// Larger masks use a general lane permute.
-template <int MASK>
-__device__ __forceinline__ int xor_lane_b32(int v) {
-  if constexpr (MASK == 1) return __builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, true);
-  else if constexpr (MASK == 2) return __builtin_amdgcn_mov_dpp(v, 0x4E, 0xF, 0xF, true);
-  else if constexpr (MASK == 4)
-    return __builtin_amdgcn_mov_dpp(__builtin_amdgcn_mov_dpp(v, 0x141, 0xF, 0xF, true), 0x1B, 0xF,
-                                    0xF, true);
-  else if constexpr (MASK == 8) return __builtin_amdgcn_mov_dpp(v, 0x128, 0xF, 0xF, true);
-  else return __shfl_xor(v, MASK, 64);
-}
-
-template <int MASK>
-__device__ __forceinline__ float xor_lane(float v) {
-  return __builtin_bit_cast(float, xor_lane_b32<MASK>(__builtin_bit_cast(int, v)));
-}
-template <int MASK>
-__device__ __forceinline__ double xor_lane(double v) {
-  const long long b = __builtin_bit_cast(long long, v);
-  const int lo = xor_lane_b32<MASK>((int)b), hi = xor_lane_b32<MASK>((int)(b >> 32));
-  return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned)lo);
-}
-
 // y stages of the transform: stage b exchanges with lane y ^ 2^b
 template <typename T, int L, int B = 0>
 __device__ __forceinline__ void y_stages(T (&w)[1 << L], const T (&sgn)[L > 0 ? L : 1]) {
