@@ -48,6 +48,8 @@ struct BwdK {
   const T* fin;      // residual form: right-hand side
   const T* C;        // SIRT: inverse column sums
   const BwdAngle* ang;
+  const double* fwd_part;   // CGLS: the forward projection's per-block ||q||^2 partials
+  int fwd_blocks;
   SolverState* st;
   RedScratch red;
   int n, nb, m;
@@ -254,15 +256,18 @@ template <typename T, int MODE>
 __device__ __forceinline__ void backward_body(const BwdK<T>& a, const BlockPos pos) {
   constexpr int G = kGroups<T>;
   if (a.st && a.st->done) return;   // solver finished: later launches are no-ops
-  // CGLS: this iteration's step length and the previous direction coefficient
-  // (the last block overwrites beta only after every block has read it)
+  // CGLS: the previous direction coefficient (the last block overwrites beta
+  // only after every block has read it); this iteration's step length is
+  // formed below from the forward projection's partial sums
   double alpha = 0.0, beta = 0.0;
   if constexpr (MODE == BWD_CGLS || MODE == BWD_CGLS_INIT) {
-    alpha = a.st->alpha;
+    alpha = a.st->alpha;   // zero before the first iteration
     beta = a.st->beta;
   }
+  int degen = 0;           // CGLS: delta not positive and finite (no step)
   __shared__ T win[G][2][kChunk * kWin];
   __shared__ Meta<T> meta[G][3][kChunk];
+  __shared__ double qsh[G * 2];   // CGLS: per-wave sums of the ||q||^2 partials
   // the groups' partial sums reuse the window memory once the angle loop is done
   static_assert(G * 2 * kThreads <= G * 2 * kChunk * kWin, "partials must fit in the window");
   T (*part)[2][kThreads] = reinterpret_cast<T (*)[2][kThreads]>(&win[0][0][0]);
@@ -287,17 +292,44 @@ __device__ __forceinline__ void backward_body(const BwdK<T>& a, const BlockPos p
   // third, then the first chunk's window straight into LDS
   {
     const int k0 = grp * kChunk;
+    Raw<T> r0, r1;
     if (rawwave) {
-      Raw<T> r0, r1;
       load_raw<T>(r0, a.ang, k0, t, m);
       load_raw<T>(r1, a.ang, k0 + kAhead, t, m);
       load_raw<T>(ahead, a.ang, k0 + 2 * kAhead, t, m);
+    }
+    if constexpr (MODE == BWD_CGLS) {
+      // ||q||^2 from the forward projection's per-block partial sums (loaded
+      // beside the angle records), summed in the same fixed order by every
+      // block: per thread over blocks tid, tid + blockDim, ..., then per wave
+      // (published before the barrier below), then the waves in order
+      double qq = 0.0;
+      for (int b = threadIdx.x; b < a.fwd_blocks; b += kThreads * G) qq += a.fwd_part[b];
+      qq = wave_sum(qq);
+      if ((threadIdx.x & 63) == 0) qsh[threadIdx.x >> 6] = qq;
+    }
+    if (rawwave) {
       fill_meta<T>(meta[grp][0], r0, k0, t, m, Xc, Yc, hb);
       fill_meta<T>(meta[grp][1], r1, k0 + kAhead, t, m, Xc, Yc, hb);
     }
     __syncthreads();
     Stage<T, MODE> sg;
     stage_load<T, MODE>(sg, a, meta[grp][0], grp * kChunk, t);
+    if constexpr (MODE == BWD_CGLS) {
+      // while the first window loads are in flight: delta = ||q||^2 +
+      // lambda ||p||^2 and alpha = gamma / delta, the same in every block;
+      // block 0 stores them for the next forward projection
+      double qq = 0.0;
+#pragma unroll
+      for (int w = 0; w < G * 2; ++w) qq += qsh[w];
+      const double delta = qq + a.st->lambda * a.st->pp;
+      degen = cgls_degenerate(delta);
+      alpha = degen ? 0.0 : a.st->gamma / delta;
+      if (pos.id() == 0 && threadIdx.x == 0) {
+        a.st->alpha = alpha;
+        a.st->delta = delta;
+      }
+    }
     stage_store<T, MODE>(sg, win[grp][0], alpha, t);
     __syncthreads();
   }
@@ -394,8 +426,13 @@ __device__ __forceinline__ void backward_body(const BwdK<T>& a, const BlockPos p
           const size_t px = (size_t)iy * n + ix;
           T xn;
           if constexpr (MODE == BWD_CGLS) {
-            pv = (T)((double)z_in[q] + beta * (double)p_in[q]);
-            xn = (T)((double)x_in[q] + alpha * (double)pv);
+            if (!degen) {
+              pv = (T)((double)z_in[q] + beta * (double)p_in[q]);
+              xn = (T)((double)x_in[q] + alpha * (double)pv);
+            } else {   // no step: direction and iterate stay as they are
+              pv = p_in[q];
+              xn = x_in[q];
+            }
           } else {
             xn = x_in[q];
           }
@@ -446,8 +483,9 @@ __device__ __forceinline__ void backward_body(const BwdK<T>& a, const BlockPos p
     }
     SolverState* sst = a.st;
     reduce_and_finish<4, kThreads * G / 64>(v, a.red, pos.count(), pos.id(),
-                                            [sst](double (&tot)[4]) {
-                                              cgls_precond_finish(sst, tot, MODE == BWD_CGLS_INIT);
+                                            [sst, degen](double (&tot)[4]) {
+                                              cgls_precond_finish(sst, tot, MODE == BWD_CGLS_INIT,
+                                                                  degen);
                                             });
     if constexpr (MODE == BWD_CGLS) {
       if (grp == 0) {
@@ -564,6 +602,8 @@ BwdK<T> bwd_args(const Geometry& g, const BwdArgs& a) {
   k.fin = (const T*)a.f;
   k.C = (const T*)a.C;
   k.ang = g.d_bwd;
+  k.fwd_part = a.fwd_part;
+  k.fwd_blocks = a.fwd_blocks;
   k.st = a.st;
   k.red = a.red;
   k.n = g.n;

@@ -236,6 +236,8 @@ class Engine {
     a.identity = s.o.precond == RECO_PRECOND_NONE;
     a.st = s.w->st;
     a.red = red_of(*s.w, 1);
+    a.fwd_part = fwd_partials(*s.w);
+    a.fwd_blocks = forward_blocks(*s.g);
     return a;
   }
   static WmgArgs wmg_of(const Slot& s) {
@@ -276,7 +278,7 @@ class Engine {
       f.out = w.q;
       f.r = w.r;
       f.st = w.st;
-      f.red = red_of(w, 0);
+      f.part = fwd_partials(w);
       fa.push_back(f);
       ba.push_back(bwd_of(*s));
       if (!backward_fuses_wmg(*s->g)) {

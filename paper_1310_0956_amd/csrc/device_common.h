@@ -156,8 +156,18 @@ __device__ __forceinline__ bool finite(double v) { return __builtin_isfinite(v);
 // iteration (z_0 = M^-1 s_0, gamma_0 = <s_0,z_0>, reference norm ||s_0||).
 // Otherwise: beta = gamma'/gamma, the squared norm of the next direction
 // z + beta p, the relative residual ||s|| / ||s_0|| and the stopping test.
+// degen (the iteration's delta = ||q||^2 + lambda ||p||^2 was not positive
+// and finite: 1 zero, 3 non-finite): the iteration took no step; the solve
+// ends with that code and the iteration is not counted.
+__device__ __forceinline__ int cgls_degenerate(double delta) {
+  return !finite(delta) ? 3 : (delta <= 0.0 ? 1 : 0);
+}
 __device__ __forceinline__ void cgls_precond_finish(SolverState* st, const double (&t)[4],
-                                                    bool init) {
+                                                    bool init, int degen = 0) {
+  if (degen) {
+    st->done = degen;
+    return;
+  }
   if (init) {
     st->gamma = t[0];
     st->s0 = sqrt(t[1]);

@@ -179,7 +179,9 @@ struct FwdArgs {
   const void* b;       // SIRT: measured data
   const void* R;       // SIRT: inverse row sums
   SolverState* st;     // CGLS/SIRT: state (may be null)
-  RedScratch red;      // CGLS: partials
+  RedScratch red;      // unused by the CGLS mode
+  double* part;        // CGLS: per-block ||q||^2 partial sums (plain stores; the next
+                       // backprojection sums them)
   unsigned long long* count;  // FWD_COUNT: nnz counter
 };
 
@@ -201,6 +203,10 @@ struct BwdArgs {
   void* zP = nullptr;            // padded z (read: previous z; written: new z)
   void* zTP = nullptr;           // padded transposed z (written)
   bool identity = false;         // no preconditioner: z = s
+  // CGLS: the preceding forward projection's per-block ||q||^2 partial sums,
+  // from which every block forms this iteration's step length
+  const double* fwd_part = nullptr;
+  int fwd_blocks = 0;
 };
 // True when the CGLS backprojection also applies the WMG preconditioner.
 bool backward_fuses_wmg(const Geometry& g);

@@ -64,6 +64,7 @@ struct FwdK {
   int nbx, maxb;
   SolverState* st;
   RedScratch red;
+  double* part;        // CGLS: per-block ||q||^2 partial sums
   unsigned long long* count;
   int n, ld, nb, m;
   double h;
@@ -443,33 +444,21 @@ __device__ __forceinline__ void forward_body(const FwdK<T>& a, const BlockPos bp
     if (valid) a.out[i] = (T)((double)a.R[i] * ((double)a.b[i] - (double)result));
   } else if constexpr (MODE == FWD_CGLS) {
     // The residual update of the previous iteration, r -= alpha q_old (alpha
-    // of that iteration: this launch's last block overwrites it only after
-    // every block has read it), then
+    // of that iteration, stored by the previous backprojection), then
     // q = W z + beta q_old  (q_old = W p_old, so q = W (z + beta p_old) = W p_new)
-    // The new r and q are stored after the block has taken its reduction
-    // ticket (whose wait covers the wave's pending stores).
+    // and the block's part of ||q||^2: a plain store, summed by every block of
+    // the following backprojection (kernel boundaries make it visible), which
+    // forms delta and the step length alpha from it.
     double q = 0.0, r_new = 0.0;
     if (valid) {
       const double q_old = (double)a.out[i];
       r_new = (double)a.r[i] - alpha_prev * q_old;
       q = (double)(T)((double)result + a.st->beta * q_old);
     }
+    __shared__ double sh[kThreads / 64];
     double v[1] = {q * q};
-    SolverState* st = a.st;
-    reduce_and_finish<1, kThreads / 64>(v, a.red, bp.count(), bp.id(),
-                                        [st](double (&tot)[1]) {
-                                          const double delta = tot[0] + st->lambda * st->pp;
-                                          st->delta = delta;
-                                          if (!finite(delta)) {
-                                            st->done = 3;
-                                            st->alpha = 0.0;
-                                          } else if (delta <= 0.0) {
-                                            st->done = 1;   // zero direction: nothing to do
-                                            st->alpha = 0.0;
-                                          } else {
-                                            st->alpha = st->gamma / delta;
-                                          }
-                                        });
+    block_sum<1, kThreads / 64>(v, sh);
+    if (threadIdx.x == 0) a.part[bp.id()] = v[0];
     if (valid) {
       a.r[i] = (T)r_new;
       a.out[i] = (T)q;
@@ -570,6 +559,7 @@ FwdK<T> make_args(const Geometry& g, const FwdArgs& a) {
   k.rows = (const int2*)g.d_fwd_rows;
   k.wins = (const int2*)g.d_fwd_wins;
   k.order = g.d_fwd_order;
+  k.part = a.part;
   k.nbx = (g.nb + kBins - 1) / kBins;
   k.maxb = g.fwd_maxb;
   k.st = a.st;

@@ -49,7 +49,7 @@ Workspace* checkout_workspace(Geometry& g, hipStream_t st) {
   alloc(&w->zTP, es * g.padded_elems());
   int cap = std::max(forward_blocks(g), std::max(backward_blocks(g), wmg_blocks(g)));
   w->red_cap = cap * 4;
-  alloc((void**)&w->partial, sizeof(double) * w->red_cap);
+  alloc((void**)&w->partial, sizeof(double) * (w->red_cap + cap));
   alloc((void**)&w->counter, sizeof(unsigned) * 4);
   alloc((void**)&w->st, sizeof(SolverState));
   if (hipHostMalloc((void**)&w->h_st, sizeof(SolverState), hipHostMallocDefault) != hipSuccess)
@@ -111,6 +111,8 @@ void ensure_history(Workspace& w, int cap) {
   alloc((void**)&w.hist, sizeof(double) * cap);
   w.hist_cap = cap;
 }
+
+double* fwd_partials(Workspace& w) { return w.partial + w.red_cap; }
 
 RedScratch red_of(Workspace& w, int slot) {
   RedScratch r;
@@ -207,11 +209,11 @@ static FwdArgs cgls_fwd_args(Workspace& w) {
   fa.out = w.q;
   fa.r = w.r;
   fa.st = w.st;
-  fa.red = red_of(w, 0);
+  fa.part = fwd_partials(w);
   return fa;
 }
 
-static BwdArgs cgls_bwd_args(Workspace& w, void* x, const reco_solve_opts& o) {
+static BwdArgs cgls_bwd_args(const Geometry& g, Workspace& w, void* x, const reco_solve_opts& o) {
   BwdArgs ba{};
   ba.sino = w.r;
   ba.q = w.q;
@@ -223,6 +225,8 @@ static BwdArgs cgls_bwd_args(Workspace& w, void* x, const reco_solve_opts& o) {
   ba.identity = o.precond == RECO_PRECOND_NONE;
   ba.st = w.st;
   ba.red = red_of(w, 1);
+  ba.fwd_part = fwd_partials(w);
+  ba.fwd_blocks = forward_blocks(g);
   return ba;
 }
 
@@ -241,7 +245,7 @@ static WmgArgs cgls_wmg_args(Workspace& w, const reco_solve_opts& o) {
 
 void cgls_iteration(Geometry& g, Workspace& w, void* x, const reco_solve_opts& o, hipStream_t st) {
   launch_forward(g, FWD_CGLS, cgls_fwd_args(w), st);
-  launch_backward(g, BWD_CGLS, cgls_bwd_args(w, x, o), st);
+  launch_backward(g, BWD_CGLS, cgls_bwd_args(g, w, x, o), st);
   if (!backward_fuses_wmg(g)) launch_wmg(g, WMG_CGLS, cgls_wmg_args(w, o), st);
 }
 
@@ -256,7 +260,7 @@ void cgls_setup(Geometry& g, Workspace& w, const void* b, void* x, const reco_so
   launch_fill(w.p, g.N(), g.f64, 0.0, st);
   launch_fill(w.q, g.M(), g.f64, 0.0, st);
   launch_copy(b, w.r, g.M(), g.f64, st);
-  launch_backward(g, BWD_CGLS_INIT, cgls_bwd_args(w, x, o), st);
+  launch_backward(g, BWD_CGLS_INIT, cgls_bwd_args(g, w, x, o), st);
   if (!backward_fuses_wmg(g)) launch_wmg(g, WMG_CGLS_INIT, cgls_wmg_args(w, o), st);
 }
 

@@ -138,7 +138,8 @@ __device__ __forceinline__ void wmg_body(const WmgK<T>& a, const BlockPos bp) {
     }
     SolverState* st = a.st;
     reduce_and_finish<4>(v, a.red, bp.count(), bp.id(), [st](double (&t)[4]) {
-      cgls_precond_finish(st, t, MODE == WMG_CGLS_INIT);
+      cgls_precond_finish(st, t, MODE == WMG_CGLS_INIT,
+                          MODE == WMG_CGLS ? cgls_degenerate(st->delta) : 0);
     });
   }
 }
