@@ -274,6 +274,11 @@ def batch_leg(reco, torch, count):
     }
 
 
+def progress(msg):
+    """A progress line on stderr (stdout carries only the result line)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def serve_setup(reco, torch, count):
     """The served requests (sizes and seeds of the serving mix; they do not
     depend on the arrival rate), their data, and the one-at-a-time baseline:
@@ -288,11 +293,14 @@ def serve_setup(reco, torch, count):
         if k not in geo:
             geo[k] = reco.Geometry(r.side, r.n_angles, r.n_bins, inputs.default_levels(r.side),
                                    reco.F32)
+    progress(f"serving: {len(geo)} geometries for {count} requests")
     gs = [geo[(r.side, r.n_angles)] for r in mix]
     bs = [gpu_sinogram(torch, g, r.n_ellipses, r.seed, r.noise) for g, r in zip(gs, mix)]
     xs = [g.new_image() for g in gs]
     solo_ms, built = [], set()
-    for g, b, x, r in zip(gs, bs, xs, mix):
+    for i, (g, b, x, r) in enumerate(zip(gs, bs, xs, mix)):
+        if i % 100 == 0:
+            progress(f"serving: solo baseline {i}/{count}")
         torch.cuda.synchronize()
         s0 = time.perf_counter()
         if (r.side, r.n_angles) not in built:
@@ -318,6 +326,7 @@ def serve_run(reco, torch, S, rate, budget_gib, slots):
         start = max(free_at, a)
         free_at = start + ms * 1e-3
         fifo_lat.append((free_at - a) * 1e3)
+    progress(f"serving: {count} requests at {rate:.1f}/s, budget {budget_gib} GiB")
     srv = reco.Server(int(budget_gib * (1 << 30)), max_slots=slots)
     tickets = [None] * count
     outs = [g.new_image() for g in gs]
@@ -334,10 +343,18 @@ def serve_run(reco, torch, S, rate, budget_gib, slots):
     th = threading.Thread(target=submitter)
     th.start()
     res = [None] * count
-    while any(v is None for v in res):
-        for i in range(count):
-            if res[i] is None and tickets[i] is not None:
+    pending, last = list(range(count)), time.time()
+    while pending:
+        still = []
+        for i in pending:
+            if tickets[i] is not None:
                 res[i] = srv.poll(tickets[i])
+            if res[i] is None:
+                still.append(i)
+        pending = still
+        if time.time() - last > 30:
+            progress(f"serving: {count - len(pending)}/{count} done")
+            last = time.time()
         time.sleep(0.0005)
     th.join()
     srv.close()
