@@ -264,6 +264,14 @@ class Engine {
 
   void rebuild() {
     drop_graph();
+    // Largest problems first: a batched launch's blocks are dispatched in
+    // grid order, so the longest work starts first and the small problems'
+    // blocks fill in behind it.  (Results do not depend on the order.)
+    std::stable_sort(active_.begin(), active_.end(), [](const Slot* a, const Slot* b) {
+      const double ca = (double)a->g->n * a->g->n * a->g->m;
+      const double cb = (double)b->g->n * b->g->n * b->g->m;
+      return ca > cb;
+    });
     std::vector<const Geometry*> gs, gw;
     std::vector<FwdArgs> fa;
     std::vector<BwdArgs> ba;
