@@ -100,8 +100,14 @@ Geometry* create_geometry(const reco_geometry_desc& d, hipStream_t st) {
   if (d.reserved != 0) fail(RECO_EINVAL, "reserved must be 0");
   const int L = d.wmg_levels - 1;
   if (d.n % (1 << L) != 0) fail(RECO_EINVAL, "n must be divisible by 2^(wmg_levels-1)");
-  if ((double)d.n_angles * d.n_bins > 2.0e9 || (double)d.n * d.n > 2.0e9)
-    fail(RECO_EINVAL, "problem too large for 32-bit indexing");
+  // The projectors address the padded image copies and the sinogram with
+  // 32-bit byte offsets (buffer loads): each must stay below 2^31 bytes.
+  const double es = d.dtype == RECO_F64 ? 8.0 : 4.0;
+  if ((double)d.n * (d.n + 2 * kPad) * es >= 2147483648.0)
+    fail(RECO_EINVAL, "image too large: a padded image copy must stay below 2^31 bytes "
+                      "(n <= 23166 for RECO_F32, 16380 for RECO_F64)");
+  if ((double)d.n_angles * d.n_bins * es >= 2147483648.0)
+    fail(RECO_EINVAL, "sinogram too large: n_angles * n_bins * element size must stay below 2^31");
 
   std::unique_ptr<Geometry> g(new Geometry());
   g->desc = d;
