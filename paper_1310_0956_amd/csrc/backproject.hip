@@ -157,32 +157,67 @@ __device__ __forceinline__ T pixel_term(T J, const T* __restrict__ w, const Meta
   return fma(w0, r0, fma(w1, r1, acc));
 }
 
-// Raw window loads of one chunk: element e = t + kThreads*i of the chunk's
-// [kChunk][kWin] window.  Every load is issued unconditionally (from bin 0
-// for elements outside the sinogram, masked afterwards), so they are all in
-// flight together; in the CGLS modes the projected direction is loaded too.
+// Raw window loads of one chunk.  Thread t stages angle row t / 4 of the
+// chunk's [kChunk][kWin] window, bins t % 4 + 4 i, so its elements share one
+// window start and one row offset, and the lanes of a quad read consecutive
+// bins.  Bins outside [0, nb) and rows past the last angle are read at an
+// offset past the end of the buffer, which loads 0; every load is issued
+// unconditionally, so they are all in flight together.  In the CGLS modes the
+// projected direction is loaded at the same offsets.
 constexpr bool kCglsMode(int mode) { return mode == BWD_CGLS || mode == BWD_CGLS_INIT; }
+static_assert(kThreads == 4 * kChunk && kWin == 4 * kPerThread, "one window row per quad");
 
 template <typename T, int MODE>
 struct Stage {
   T r[kPerThread];
   T q[kCglsMode(MODE) ? kPerThread : 1];
-  unsigned valid;
+};
+
+// Buffers of the window loads: the sinogram operand and, in the CGLS modes,
+// the projected direction, both [m][nb].
+struct StageSrc {
+  __amdgpu_buffer_rsrc_t sino, q;
 };
 
 template <typename T, int MODE>
-__device__ __forceinline__ void stage_load(Stage<T, MODE>& sg, const BwdK<T>& a,
-                                           const Meta<T>* __restrict__ mt, int k0, int t) {
-  sg.valid = 0;
+__device__ __forceinline__ StageSrc stage_src(const BwdK<T>& a) {
+  const size_t bytes = (size_t)a.m * a.nb * sizeof(T);
+  StageSrc src;
+  src.sino = buffer_rsrc(a.sino, bytes);
+  src.q = kCglsMode(MODE) ? buffer_rsrc(a.q, bytes) : src.sino;
+  return src;
+}
+
+// rowoff = (t / 4) * nb, the thread's row offset within a chunk, taken once.
+template <typename T, int MODE>
+__device__ __forceinline__ void stage_load(Stage<T, MODE>& sg, const StageSrc& src,
+                                           const Meta<T>* __restrict__ mt, int k0, int m, int nb,
+                                           unsigned rowoff, int t) {
+  const int kk = t >> 2;
+  const int j0 = mt[kk].jw + (t & 3);
+  const bool row = kk < m - k0;
+  // byte offset of bin j0 of angle k0 + kk (valid bins lie below 2^31 bytes)
+  const unsigned off0 = ((unsigned)k0 * (unsigned)nb + rowoff + (unsigned)j0) * (unsigned)sizeof(T);
+  const bool full = row && j0 >= 0 && j0 + 4 * (kPerThread - 1) < nb;
+  if (__builtin_amdgcn_ballot_w64(!full) == 0) {
+    // the whole wave's windows lie on the detector (the common case)
 #pragma unroll
-  for (int i = 0; i < kPerThread; ++i) {
-    const int e = t + kThreads * i, kk = e / kWin, jj = e % kWin;
-    const int j = mt[kk].jw + jj;
-    const bool ok = k0 + kk < a.m && j >= 0 && j < a.nb;
-    const size_t idx = ok ? (size_t)(k0 + kk) * a.nb + j : 0;
-    sg.r[i] = a.sino[idx];
-    if constexpr (kCglsMode(MODE)) sg.q[i] = a.q[idx];
-    sg.valid |= (ok ? 1u : 0u) << i;
+    for (int i = 0; i < kPerThread; ++i) {
+      const unsigned off = off0 + 4u * i * (unsigned)sizeof(T);
+      sg.r[i] = load_elem(src.sino, off, 0, T(0));
+      if constexpr (kCglsMode(MODE)) sg.q[i] = load_elem(src.q, off, 0, T(0));
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < kPerThread; ++i) {
+      unsigned off = row && (unsigned)(j0 + 4 * i) < (unsigned)nb ? off0 : kOutside;
+      // keeps the element's constant offset out of the select, so that it
+      // becomes the load's immediate offset
+      asm volatile("" : "+v"(off));
+      off += 4u * i * (unsigned)sizeof(T);
+      sg.r[i] = load_elem(src.sino, off, 0, T(0));
+      if constexpr (kCglsMode(MODE)) sg.q[i] = load_elem(src.q, off, 0, T(0));
+    }
   }
 }
 
@@ -192,11 +227,12 @@ __device__ __forceinline__ void stage_load(Stage<T, MODE>& sg, const BwdK<T>& a,
 template <typename T, int MODE>
 __device__ __forceinline__ void stage_store(const Stage<T, MODE>& sg, T* __restrict__ w,
                                             double alpha, int t) {
+  T* row = w + (t >> 2) * kWin + (t & 3);
 #pragma unroll
   for (int i = 0; i < kPerThread; ++i) {
     T v = sg.r[i];
     if constexpr (kCglsMode(MODE)) v = (T)((double)sg.r[i] - alpha * (double)sg.q[i]);
-    w[t + kThreads * i] = ((sg.valid >> i) & 1u) ? v : T(0);
+    row[4 * i] = v;
   }
 }
 
@@ -277,6 +313,9 @@ __device__ __forceinline__ void backward_body(const BwdK<T>& a, const BlockPos p
   const int ix = pos.x * kTile + tx;
   const int iy0 = pos.y * kTile + ty, iy1 = iy0 + 8;
   const int n = a.n, nb = a.nb, m = a.m;
+  const StageSrc src = stage_src<T, MODE>(a);
+  unsigned rowoff = (unsigned)(t >> 2) * (unsigned)nb;
+  asm volatile("" : "+v"(rowoff));   // kept as is: not refolded into a product per chunk
   const double hc = 0.5 * (n - 1), hb = uniform(0.5 * (nb - 1));
   const double Xc = uniform(pos.x * kTile + 0.5 * (kTile - 1) - hc);
   const double Yc = uniform(pos.y * kTile + 0.5 * (kTile - 1) - hc);
@@ -314,7 +353,7 @@ __device__ __forceinline__ void backward_body(const BwdK<T>& a, const BlockPos p
     }
     __syncthreads();
     Stage<T, MODE> sg;
-    stage_load<T, MODE>(sg, a, meta[grp][0], grp * kChunk, t);
+    stage_load<T, MODE>(sg, src, meta[grp][0], grp * kChunk, m, nb, rowoff, t);
     if constexpr (MODE == BWD_CGLS) {
       // while the first window loads are in flight: delta = ||q||^2 +
       // lambda ||p||^2 and alpha = gamma / delta, the same in every block;
@@ -345,7 +384,7 @@ __device__ __forceinline__ void backward_body(const BwdK<T>& a, const BlockPos p
     // start the next chunk's window loads; they are consumed after the
     // current chunk is done
     Stage<T, MODE> pre;
-    if (more) stage_load<T, MODE>(pre, a, meta[grp][mnext], k1, t);
+    if (more) stage_load<T, MODE>(pre, src, meta[grp][mnext], k1, m, nb, rowoff, t);
     // compute the current chunk
     const Meta<T>* __restrict__ mt = meta[grp][mcur];
 #pragma unroll 4

@@ -148,6 +148,26 @@ __device__ __forceinline__ void reduce_and_finish(double (&v)[W], const RedScrat
   }
 }
 
+// Buffer resource over a device array of `bytes` < 2^31 bytes (geometry
+// validation bounds every image copy and sinogram): loads at byte offsets at
+// or past the end read 0 instead of faulting.
+constexpr int kBufferFlags = 0x00020000;   // raw 32-bit dword access (gfx9 family)
+constexpr unsigned kOutside = 0x80000000u; // an offset past the end of every such buffer
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_rsrc(const void* p, size_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes,
+                                           kBufferFlags);
+}
+
+__device__ __forceinline__ float load_elem(__amdgpu_buffer_rsrc_t rs, unsigned voff, int soff, float) {
+  return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, voff, soff, 0));
+}
+__device__ __forceinline__ double load_elem(__amdgpu_buffer_rsrc_t rs, unsigned voff, int soff, double) {
+  const auto v = __builtin_amdgcn_raw_buffer_load_b64(rs, voff, soff, 0);
+  const unsigned lo = v[0], hi = v[1];
+  return __hiloint2double((int)hi, (int)lo);
+}
+
 __device__ __forceinline__ bool finite(double v) { return __builtin_isfinite(v); }
 
 // End of the preconditioning step of a CGLS iteration, run once by the last

@@ -70,23 +70,6 @@ struct FwdK {
   double h;
 };
 
-constexpr int kBufferFlags = 0x00020000;   // raw 32-bit dword access (gfx9 family)
-
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t image_rsrc(const void* img, size_t bytes) {
-  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(img), (short)0, (int)bytes,
-                                           kBufferFlags);
-}
-
-// Buffer loads: offsets past the image read 0.
-__device__ __forceinline__ float load_elem(__amdgpu_buffer_rsrc_t rs, unsigned voff, int soff, float) {
-  return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, voff, soff, 0));
-}
-__device__ __forceinline__ double load_elem(__amdgpu_buffer_rsrc_t rs, unsigned voff, int soff, double) {
-  const auto v = __builtin_amdgcn_raw_buffer_load_b64(rs, voff, soff, 0);
-  const unsigned lo = v[0], hi = v[1];
-  return __hiloint2double((int)hi, (int)lo);
-}
-
 __device__ __forceinline__ int iclamp(int v, int lo, int hi) { return min(max(v, lo), hi); }
 
 // Weight of the left candidate from the fraction (float and double forms).
@@ -336,7 +319,7 @@ __device__ __forceinline__ void forward_body(const FwdK<T>& a, const BlockPos bp
   const FwdAngle ang = a.ang[k];
   const FwdAngle ang0 = a.ang[k0];
   const T* img = ang0.major ? a.imgTP : a.imgP;
-  const __amdgpu_buffer_rsrc_t rs = image_rsrc(img, (size_t)n * a.ld * sizeof(T));
+  const __amdgpu_buffer_rsrc_t rs = buffer_rsrc(img, (size_t)n * a.ld * sizeof(T));
   const double P0 = fma((double)j, ang.inv, ang.A0);
   // rows the block's rays touch and the column window of each band (setup table)
   const int blk = lb;
