@@ -50,6 +50,7 @@ struct BwdK {
   const BwdAngle* ang;
   const double* fwd_part;   // CGLS: the forward projection's per-block ||q||^2 partials
   int fwd_blocks;
+  double* slots;            // CGLS (fused WMG): finisher reduction slots
   SolverState* st;
   RedScratch red;
   int n, nb, m;
@@ -448,8 +449,8 @@ __device__ __forceinline__ void backward_body(const BwdK<T>& a, const BlockPos p
   if constexpr (MODE == BWD_CGLS || MODE == BWD_CGLS_INIT) {
     // s = W^T r - lambda x for the tile's pixels, after p = z + beta p and
     // x += alpha p; then z = M^-1 s on the tile and the four dot products.
-    // With the WMG apply fused, p, x and z are stored after the block has
-    // taken its reduction ticket (whose wait covers the wave's pending stores).
+    // With the WMG apply fused, the dot products go to the finisher
+    // reduction, then p, x and z are stored.
     T* lds = &win[0][0][0] + G * 2 * kThreads;   // past the partial sums
     T (*stile)[kTile + 1] = reinterpret_cast<T (*)[kTile + 1]>(lds);
     T (*ptile)[kTile + 1] = reinterpret_cast<T (*)[kTile + 1]>(lds + kTile * (kTile + 1));
@@ -521,11 +522,12 @@ __device__ __forceinline__ void backward_body(const BwdK<T>& a, const BlockPos p
       if (MODE == BWD_CGLS && lambda != 0.0) v[3] = zd * (double)p_own;
     }
     SolverState* sst = a.st;
-    reduce_and_finish<4, kThreads * G / 64>(v, a.red, pos.count(), pos.id(),
-                                            [sst, degen](double (&tot)[4]) {
-                                              cgls_precond_finish(sst, tot, MODE == BWD_CGLS_INIT,
-                                                                  degen);
-                                            });
+    reduce_to_finisher<4, kThreads * G / 64>(v, a.slots, pos.count(), pos.id(),
+                                             [sst, degen](double (&tot)[4], bool late) {
+                                               if (late) sst->done = 4;
+                                               else cgls_precond_finish(sst, tot,
+                                                                        MODE == BWD_CGLS_INIT, degen);
+                                             });
     if constexpr (MODE == BWD_CGLS) {
       if (grp == 0) {
 #pragma unroll
@@ -643,6 +645,7 @@ BwdK<T> bwd_args(const Geometry& g, const BwdArgs& a) {
   k.ang = g.d_bwd;
   k.fwd_part = a.fwd_part;
   k.fwd_blocks = a.fwd_blocks;
+  k.slots = a.slots;
   k.st = a.st;
   k.red = a.red;
   k.n = g.n;

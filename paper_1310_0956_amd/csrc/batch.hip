@@ -238,6 +238,7 @@ class Engine {
     a.red = red_of(*s.w, 1);
     a.fwd_part = fwd_partials(*s.w);
     a.fwd_blocks = forward_blocks(*s.g);
+    a.slots = fin_slots(*s.w);
     return a;
   }
   static WmgArgs wmg_of(const Slot& s) {

@@ -168,6 +168,79 @@ __device__ __forceinline__ double load_elem(__amdgpu_buffer_rsrc_t rs, unsigned 
   return __hiloint2double((int)hi, (int)lo);
 }
 
+// A reduction without a ticket, for kernels whose blocks are all dispatched
+// before the last one (no block waits for another to start).  Every block
+// stores its W partial sums into its slots with write-through stores and
+// goes on without waiting; the block dispatched last (block_id nblocks - 1)
+// then polls all slots until none holds the empty mark, sums them in the
+// fixed order of reduce_and_finish, marks them empty again for the next use
+// and calls fin(totals, late) from thread 0.  The slots must hold the empty
+// mark on entry (they are filled with it when allocated).  The blocks it
+// waits for hold nothing it needs, so the poll ends; it still gives up after
+// kPollTicks of the 100 MHz constant clock and then passes late = true.
+// Non-finisher blocks return at once: their bulk stores need no ordering.
+constexpr unsigned long long kPollTicks = 1000000000ull;   // 10 s
+
+template <int W, int NW = 4, typename F>
+__device__ __forceinline__ void reduce_to_finisher(double (&v)[W], double* __restrict__ slots,
+                                                   int nblocks, int block_id, F fin) {
+  __shared__ double sh[NW * W];
+  __shared__ int late;
+  if (threadIdx.x == 0) late = 0;
+  block_sum<W, NW>(v, sh);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int i = 0; i < W; ++i)
+      __hip_atomic_store(&slots[(size_t)block_id * W + i], v[i], __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_AGENT);
+  }
+  if (block_id != nblocks - 1) return;
+  unsigned long long* bits = reinterpret_cast<unsigned long long*>(slots);
+  const unsigned long long t0 = __builtin_amdgcn_s_memrealtime();
+  double acc[W];
+  bool full = false;
+  for (;;) {
+    // one pass over this thread's slots (blocks tid, tid + stride, ...), in
+    // batches of four blocks whose loads are all issued before the first sum
+    constexpr int kStride = NW * 64, kBatch = 4;
+    full = true;
+#pragma unroll
+    for (int i = 0; i < W; ++i) acc[i] = 0.0;
+    for (int b0 = threadIdx.x; b0 < nblocks; b0 += kBatch * kStride) {
+      unsigned long long u[kBatch][W];
+#pragma unroll
+      for (int k = 0; k < kBatch; ++k) {
+        const int b = min(b0 + k * kStride, nblocks - 1);
+#pragma unroll
+        for (int i = 0; i < W; ++i)
+          u[k][i] = __hip_atomic_load(&bits[(size_t)b * W + i], __ATOMIC_RELAXED,
+                                      __HIP_MEMORY_SCOPE_AGENT);
+      }
+#pragma unroll
+      for (int k = 0; k < kBatch; ++k) {
+        if (b0 + k * kStride < nblocks) {
+#pragma unroll
+          for (int i = 0; i < W; ++i) {
+            full = full && u[k][i] != kSlotEmpty;
+            acc[i] += __builtin_bit_cast(double, u[k][i]);
+          }
+        }
+      }
+    }
+    if (full || __builtin_amdgcn_s_memrealtime() - t0 > kPollTicks) break;
+    __builtin_amdgcn_s_sleep(8);
+  }
+  if (!full) late = 1;
+  for (int b = threadIdx.x; b < nblocks; b += NW * 64) {
+#pragma unroll
+    for (int i = 0; i < W; ++i)
+      __hip_atomic_store(&bits[(size_t)b * W + i], kSlotEmpty, __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_AGENT);
+  }
+  block_sum<W, NW>(acc, sh);
+  if (threadIdx.x == 0) fin(acc, late != 0);
+}
+
 __device__ __forceinline__ bool finite(double v) { return __builtin_isfinite(v); }
 
 // End of the preconditioning step of a CGLS iteration, run once by the last

@@ -142,6 +142,11 @@ struct SolverState {
 };
 
 // Reduction scratch handed to kernels that finish with a last-block step.
+// Empty mark of the slots of a finisher reduction (partial sums stored
+// without a ticket; see reduce_to_finisher): a signalling NaN, a pattern that
+// no arithmetic produces.
+constexpr unsigned long long kSlotEmpty = 0x7FF4C0FFEE000001ull;
+
 struct RedScratch {
   double* partial;          // [blocks * width]
   unsigned int* counter;    // zero-initialised ticket counter
@@ -207,6 +212,9 @@ struct BwdArgs {
   // from which every block forms this iteration's step length
   const double* fwd_part = nullptr;
   int fwd_blocks = 0;
+  // CGLS with the WMG apply fused: the finisher reduction's slots [blocks * 4],
+  // empty-marked between uses
+  double* slots = nullptr;
 };
 // True when the CGLS backprojection also applies the WMG preconditioner.
 bool backward_fuses_wmg(const Geometry& g);

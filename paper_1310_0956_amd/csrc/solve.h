@@ -15,7 +15,8 @@ struct Workspace {
   void *tmp = nullptr;                        // [max(N, M)]
   void *fvec = nullptr;                       // [N] right-hand side W^T b (GMRES)
   double* partial = nullptr;                  // reduction partials [red_cap], then the
-                                              // forward projection's CGLS partials [red_cap / 4]
+                                              // forward projection's CGLS partials [red_cap / 4],
+                                              // then the finisher slots [red_cap]
   unsigned* counter = nullptr;                // 4 ticket counters
   int red_cap = 0;
   SolverState* st = nullptr;                  // device state
@@ -35,6 +36,7 @@ void ensure_aux(Geometry& g, Workspace& w);     // xP, xTP, tmp, fvec
 void ensure_history(Workspace& w, int cap);
 RedScratch red_of(Workspace& w, int slot);
 double* fwd_partials(Workspace& w);             // the forward projection's CGLS partials
+double* fin_slots(Workspace& w);                // the backprojection's finisher slots (empty-marked)
 // Device bytes of one CGLS workspace / of a geometry's own tables, for the
 // geometry described by d (used for admission by memory budget).
 size_t cgls_workspace_bytes(const reco_geometry_desc& d);

@@ -49,12 +49,15 @@ Workspace* checkout_workspace(Geometry& g, hipStream_t st) {
   alloc(&w->zTP, es * g.padded_elems());
   int cap = std::max(forward_blocks(g), std::max(backward_blocks(g), wmg_blocks(g)));
   w->red_cap = cap * 4;
-  alloc((void**)&w->partial, sizeof(double) * (w->red_cap + cap));
+  alloc((void**)&w->partial, sizeof(double) * (2 * w->red_cap + cap));
   alloc((void**)&w->counter, sizeof(unsigned) * 4);
   alloc((void**)&w->st, sizeof(SolverState));
   if (hipHostMalloc((void**)&w->h_st, sizeof(SolverState), hipHostMallocDefault) != hipSuccess)
     fail(RECO_ENOMEM, "pinned host allocation failed");
   HIP_CHECK(hipMemsetAsync(w->counter, 0, sizeof(unsigned) * 4, st));
+  double empty;
+  std::memcpy(&empty, &kSlotEmpty, sizeof(empty));
+  launch_fill(fin_slots(*w), w->red_cap, true, empty, st);
   // zero padding columns of the padded image copies once; kernels only write interiors
   launch_fill(w->zP, g.padded_elems(), g.f64, 0.0, st);
   launch_fill(w->zTP, g.padded_elems(), g.f64, 0.0, st);
@@ -73,11 +76,12 @@ size_t cgls_workspace_bytes(const reco_geometry_desc& d) {
   const size_t es = d.dtype == RECO_F64 ? 8 : 4;
   const size_t n = (size_t)d.n, N = n * n, M = (size_t)d.n_angles * d.n_bins;
   const size_t padded = n * (n + 2 * kPad);
-  const size_t tiles = (n + 31) / 32;
+  const size_t tiles = (n + 15) / 16;
   const size_t fblocks = (size_t)((d.n_bins + 31) / 32) * (size_t)((d.n_angles + 7) / 8 + 2);
   const size_t blocks = std::max(fblocks, tiles * tiles) * 2;
   const size_t hist = 8 * 4096;
-  return es * (2 * M + 2 * N + 2 * padded) + sizeof(double) * 4 * blocks + hist + 4096;
+  // reduction partials, forward partials and finisher slots: 9 doubles per block
+  return es * (2 * M + 2 * N + 2 * padded) + sizeof(double) * 9 * blocks + hist + 4096;
 }
 
 size_t geometry_bytes(const reco_geometry_desc& d) {
@@ -113,6 +117,7 @@ void ensure_history(Workspace& w, int cap) {
 }
 
 double* fwd_partials(Workspace& w) { return w.partial + w.red_cap; }
+double* fin_slots(Workspace& w) { return w.partial + w.red_cap + w.red_cap / 4; }
 
 RedScratch red_of(Workspace& w, int slot) {
   RedScratch r;
@@ -145,6 +150,7 @@ reco_status status_of(int done) {
     case 1: return RECO_OK;
     case 2: return RECO_ENOTCONV;
     case 3: return RECO_ENUMERIC;
+    case 4: return RECO_EDEVICE;   // a reduction's partial sums never arrived
     default: return RECO_ENOTCONV;
   }
 }
@@ -227,6 +233,7 @@ static BwdArgs cgls_bwd_args(const Geometry& g, Workspace& w, void* x, const rec
   ba.red = red_of(w, 1);
   ba.fwd_part = fwd_partials(w);
   ba.fwd_blocks = forward_blocks(g);
+  ba.slots = fin_slots(w);
   return ba;
 }
 
