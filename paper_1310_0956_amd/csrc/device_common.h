@@ -170,8 +170,9 @@ __device__ __forceinline__ double load_elem(__amdgpu_buffer_rsrc_t rs, unsigned 
 
 // A reduction without a ticket, for kernels whose blocks are all dispatched
 // before the last one (no block waits for another to start).  Every block
-// stores its W partial sums into its slots with write-through stores and
-// goes on without waiting; the block dispatched last (block_id nblocks - 1)
+// stores its W partial sums into its slots (component-major: slot i of
+// block b at i * nblocks + b, so the finisher's loads are coalesced) with
+// write-through stores and goes on without waiting; the block dispatched last (block_id nblocks - 1)
 // then polls all slots until none holds the empty mark, sums them in the
 // fixed order of reduce_and_finish, marks them empty again for the next use
 // and calls fin(totals, late) from thread 0.  The slots must hold the empty
@@ -191,7 +192,7 @@ __device__ __forceinline__ void reduce_to_finisher(double (&v)[W], double* __res
   if (threadIdx.x == 0) {
 #pragma unroll
     for (int i = 0; i < W; ++i)
-      __hip_atomic_store(&slots[(size_t)block_id * W + i], v[i], __ATOMIC_RELAXED,
+      __hip_atomic_store(&slots[(size_t)i * nblocks + block_id], v[i], __ATOMIC_RELAXED,
                          __HIP_MEMORY_SCOPE_AGENT);
   }
   if (block_id != nblocks - 1) return;
@@ -213,7 +214,7 @@ __device__ __forceinline__ void reduce_to_finisher(double (&v)[W], double* __res
         const int b = min(b0 + k * kStride, nblocks - 1);
 #pragma unroll
         for (int i = 0; i < W; ++i)
-          u[k][i] = __hip_atomic_load(&bits[(size_t)b * W + i], __ATOMIC_RELAXED,
+          u[k][i] = __hip_atomic_load(&bits[(size_t)i * nblocks + b], __ATOMIC_RELAXED,
                                       __HIP_MEMORY_SCOPE_AGENT);
       }
 #pragma unroll
@@ -234,7 +235,7 @@ __device__ __forceinline__ void reduce_to_finisher(double (&v)[W], double* __res
   for (int b = threadIdx.x; b < nblocks; b += NW * 64) {
 #pragma unroll
     for (int i = 0; i < W; ++i)
-      __hip_atomic_store(&bits[(size_t)b * W + i], kSlotEmpty, __ATOMIC_RELAXED,
+      __hip_atomic_store(&bits[(size_t)i * nblocks + b], kSlotEmpty, __ATOMIC_RELAXED,
                          __HIP_MEMORY_SCOPE_AGENT);
   }
   block_sum<W, NW>(acc, sh);
