@@ -102,13 +102,6 @@ __device__ __forceinline__ double bits_to_double(unsigned lo, unsigned hi) {
   return __hiloint2double((int)hi, (int)lo);
 }
 
-// A wave-uniform float64 held in scalar registers (vector arithmetic leaves
-// its results in vector registers).
-__device__ __forceinline__ double uniform(double v) {
-  return __hiloint2double(__builtin_amdgcn_readfirstlane(__double2hiint(v)),
-                          __builtin_amdgcn_readfirstlane(__double2loint(v)));
-}
-
 // Ring entries of the chunk starting at angle k0 from its records (all lanes
 // of the group's first wave take part; lanes t < 32 write entry t).  The
 // float cosines are the float64 ones rounded to nearest, as in the table.
@@ -292,14 +285,30 @@ constexpr int kGroups = sizeof(T) == 4 ? 4 : 2;
 template <typename T, int MODE>
 __device__ __forceinline__ void backward_body(const BwdK<T>& a, const BlockPos pos) {
   constexpr int G = kGroups<T>;
-  if (a.st && a.st->done) return;   // solver finished: later launches are no-ops
+  // Solver state read with vector loads (an opaque zero index keeps them off
+  // the scalar path: scalar loads share one out-of-order counter with LDS, so
+  // they would be waited for before the first angle records are requested).
+  int vzero;
+  asm volatile("v_mov_b32 %0, 0" : "=v"(vzero));
+  // solver finished: later launches are no-ops (tested once the prologue's
+  // first loads are in flight; the flag is the same for every block, and
+  // nothing is stored before the test)
+  int done_v = 0;
+  if (a.st) done_v = (&a.st->done)[vzero];
   // CGLS: the previous direction coefficient (the last block overwrites beta
   // only after every block has read it); this iteration's step length is
-  // formed below from the forward projection's partial sums
+  // formed below from the forward projection's partial sums and gamma,
+  // lambda and ||p||^2
   double alpha = 0.0, beta = 0.0;
+  double alpha_v = 0.0, beta_v = 0.0, gamma_v = 0.0, lambda_v = 0.0, pp_v = 0.0;
   if constexpr (MODE == BWD_CGLS || MODE == BWD_CGLS_INIT) {
-    alpha = a.st->alpha;   // zero before the first iteration
-    beta = a.st->beta;
+    beta_v = (&a.st->beta)[vzero];
+    if constexpr (MODE == BWD_CGLS_INIT) alpha_v = (&a.st->alpha)[vzero];  // zero before the first iteration
+    if constexpr (MODE == BWD_CGLS) {
+      gamma_v = (&a.st->gamma)[vzero];
+      lambda_v = (&a.st->lambda)[vzero];
+      pp_v = (&a.st->pp)[vzero];
+    }
   }
   int degen = 0;           // CGLS: delta not positive and finite (no step)
   __shared__ T win[G][2][kChunk * kWin];
@@ -341,12 +350,27 @@ __device__ __forceinline__ void backward_body(const BwdK<T>& a, const BlockPos p
     if constexpr (MODE == BWD_CGLS) {
       // ||q||^2 from the forward projection's per-block partial sums (loaded
       // beside the angle records), summed in the same fixed order by every
-      // block: per thread over blocks tid, tid + blockDim, ..., then per wave
-      // (published before the barrier below), then the waves in order
+      // block: per thread over blocks tid, tid + blockDim, ... (eight loads in
+      // flight at a time), then per wave (published before the barrier
+      // below), then the waves in order
+      constexpr int kStride = kThreads * G, kBatch = 8;
+      const int nf = a.fwd_blocks;
       double qq = 0.0;
-      for (int b = threadIdx.x; b < a.fwd_blocks; b += kThreads * G) qq += a.fwd_part[b];
+      for (int b0 = threadIdx.x; b0 < nf; b0 += kBatch * kStride) {
+        double u[kBatch];
+#pragma unroll
+        for (int k = 0; k < kBatch; ++k) u[k] = a.fwd_part[min(b0 + k * kStride, nf - 1)];
+#pragma unroll
+        for (int k = 0; k < kBatch; ++k)
+          if (b0 + k * kStride < nf) qq += u[k];
+      }
       qq = wave_sum(qq);
       if ((threadIdx.x & 63) == 0) qsh[threadIdx.x >> 6] = qq;
+    }
+    if (__builtin_amdgcn_readfirstlane(done_v)) return;   // before any store and barrier
+    if constexpr (MODE == BWD_CGLS || MODE == BWD_CGLS_INIT) {
+      beta = uniform(beta_v);
+      alpha = uniform(alpha_v);
     }
     if (rawwave) {
       fill_meta<T>(meta[grp][0], r0, k0, t, m, Xc, Yc, hb);
@@ -362,9 +386,9 @@ __device__ __forceinline__ void backward_body(const BwdK<T>& a, const BlockPos p
       double qq = 0.0;
 #pragma unroll
       for (int w = 0; w < G * 2; ++w) qq += qsh[w];
-      const double delta = qq + a.st->lambda * a.st->pp;
+      const double delta = qq + uniform(lambda_v) * uniform(pp_v);
       degen = cgls_degenerate(delta);
-      alpha = degen ? 0.0 : a.st->gamma / delta;
+      alpha = degen ? 0.0 : uniform(gamma_v) / delta;
       if (pos.id() == 0 && threadIdx.x == 0) {
         a.st->alpha = alpha;
         a.st->delta = delta;

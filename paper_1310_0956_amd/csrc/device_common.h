@@ -47,6 +47,13 @@ __device__ __forceinline__ double read_lane(double v, int lane) {
   return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned)lo);
 }
 
+// A wave-uniform float64 held in scalar registers (vector arithmetic leaves
+// its results in vector registers).
+__device__ __forceinline__ double uniform(double v) {
+  return __hiloint2double(__builtin_amdgcn_readfirstlane(__double2hiint(v)),
+                          __builtin_amdgcn_readfirstlane(__double2loint(v)));
+}
+
 // Sum over the 64 lanes, the same value in every lane: butterflies within
 // each row of 16 lanes (DPP lane moves; every lane of a row ends with the
 // same row sum, each pairwise add being commutative), then the four row sums

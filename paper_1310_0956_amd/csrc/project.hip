@@ -296,9 +296,18 @@ template <typename T, int MODE>
 __device__ __forceinline__ void forward_body(const FwdK<T>& a, const BlockPos bp) {
   constexpr int BAND = kBand<T>;
   constexpr int STAGE_PER = BAND / kStageRows;   // loads per thread per band
-  if (a.st && a.st->done) return;   // solver finished: later launches are no-ops
-  double alpha_prev = 0.0;
-  if constexpr (MODE == FWD_CGLS) alpha_prev = a.st->alpha;
+  // Loads whose results are wanted later carry an opaque zero held in a
+  // vector register: the value then stays in vector registers until it is
+  // used, instead of being moved to scalar registers (which would wait for
+  // the load) right after it is issued.
+  int vzero;
+  asm volatile("v_mov_b32 %0, 0" : "=v"(vzero));
+  // solver finished: later launches are no-ops (tested before the first band
+  // is staged, once the block's table loads are in flight)
+  int done_v = 0;
+  if (a.st) done_v = (&a.st->done)[vzero];
+  double alpha_v = 0.0;   // CGLS: the previous iteration's step length
+  if constexpr (MODE == FWD_CGLS) alpha_v = (&a.st->alpha)[vzero];
   __shared__ T win[2][BAND * kStride];
   const int t = threadIdx.x;
   const int n = a.n, nb = a.nb;
@@ -342,13 +351,10 @@ __device__ __forceinline__ void forward_body(const FwdK<T>& a, const BlockPos bp
   Window wcur{0, 0};
   int cur_shift = 0;   // window start the walker's columns are currently relative to
   // The window of band b + 1 is loaded during band b - 1 (two bands ahead of
-  // its first use), so no band waits on the table.  The load's index carries
-  // an opaque zero held in a vector register: the value then stays in vector
-  // registers until it is used, instead of being moved to scalar registers
-  // (which would wait for the load) right after it is issued.
-  int vzero;
-  asm volatile("v_mov_b32 %0, 0" : "=v"(vzero));
+  // its first use, with the opaque zero in its index), so no band waits on
+  // the table.
   int2 wahead = make_int2(0, 0);
+  if (__builtin_amdgcn_readfirstlane(done_v)) return;   // before any store and barrier
   if (nbands > 0) {
     const int2 w0 = bandwin[0];
     if (nbands > 1) wahead = bandwin[1];
@@ -435,7 +441,7 @@ __device__ __forceinline__ void forward_body(const FwdK<T>& a, const BlockPos bp
     double q = 0.0, r_new = 0.0;
     if (valid) {
       const double q_old = (double)a.out[i];
-      r_new = (double)a.r[i] - alpha_prev * q_old;
+      r_new = (double)a.r[i] - uniform(alpha_v) * q_old;
       q = (double)(T)((double)result + a.st->beta * q_old);
     }
     __shared__ double sh[kThreads / 64];
