@@ -40,7 +40,8 @@ typedef int32_t reco_status;
 #define RECO_ENOTCONV   2   /* iteration cap reached before tol; x holds the last iterate */
 #define RECO_EINVAL    -1   /* invalid argument; nothing was enqueued */
 #define RECO_ENOMEM    -2   /* device or host allocation failed */
-#define RECO_EDEVICE   -3   /* a HIP call failed */
+#define RECO_EDEVICE   -3   /* a HIP call failed, or a device-side reduction never
+                               received its partial sums (bounded wait) */
 #define RECO_ENUMERIC  -4   /* a non-finite scalar appeared (e.g. NaN in b) */
 #define RECO_ENOTFOUND -5   /* unknown ticket */
 

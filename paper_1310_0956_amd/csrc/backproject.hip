@@ -295,8 +295,8 @@ __device__ __forceinline__ void backward_body(const BwdK<T>& a, const BlockPos p
   // nothing is stored before the test)
   int done_v = 0;
   if (a.st) done_v = (&a.st->done)[vzero];
-  // CGLS: the previous direction coefficient (the last block overwrites beta
-  // only after every block has read it); this iteration's step length is
+  // CGLS: the previous direction coefficient (the finisher overwrites beta
+  // only after every block has stored its partials, so has read it); this iteration's step length is
   // formed below from the forward projection's partial sums and gamma,
   // lambda and ||p||^2
   double alpha = 0.0, beta = 0.0;

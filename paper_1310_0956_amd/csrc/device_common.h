@@ -1,6 +1,7 @@
 // Device helpers shared by the kernels: wave64 reductions, fixed-order block
-// reductions and the last-block finalisation pattern (deterministic: partials
-// are summed in block order by whichever block finishes last).
+// reductions, the last-block finalisation pattern and the finisher pattern
+// (both deterministic: partials are summed in block order, by whichever block
+// finishes last or by the block dispatched last).
 #pragma once
 
 #include <hip/hip_runtime.h>

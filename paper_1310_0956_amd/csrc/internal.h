@@ -141,12 +141,12 @@ struct SolverState {
   double wnorm;      // norm of the last orthogonalised vector
 };
 
-// Reduction scratch handed to kernels that finish with a last-block step.
 // Empty mark of the slots of a finisher reduction (partial sums stored
 // without a ticket; see reduce_to_finisher): a signalling NaN, a pattern that
 // no arithmetic produces.
 constexpr unsigned long long kSlotEmpty = 0x7FF4C0FFEE000001ull;
 
+// Reduction scratch handed to kernels that finish with a last-block step.
 struct RedScratch {
   double* partial;          // [blocks * width]
   unsigned int* counter;    // zero-initialised ticket counter
