@@ -230,51 +230,63 @@ __device__ __forceinline__ void stage_store(const Stage<T, MODE>& sg, T* __restr
   }
 }
 
-// Walsh-Hadamard transform of every 2^L x 2^L tile of a 16 x 16 LDS tile
-// (the full Haar packet transform up to the 2^-L scale): butterflies along x,
-// then along y, one pair per thread for the first 128 threads, one barrier per
-// stage.  All threads of the block must call it.
-template <typename T, int L>
-__device__ __forceinline__ void wht16(T (*tile)[kTile + 1]) {
-  const int t = threadIdx.x;
+// The WMG apply z = H^T diag(4^-L / (d + lambda)) H s on a 16 x 16 tile (the
+// Haar packet transform of every 2^L x 2^L tile is its Walsh-Hadamard
+// transform up to the 2^-L scale; 1/0 := 0), by one wave: lane l holds the
+// pixels (l % 16, l / 16 + 4 k), k < 4.  Butterflies along x pair lanes
+// l and l ^ 2^b (lane moves within rows of 16); along y they pair lanes
+// l and l ^ 16 2^b for b < 2 (lane shuffles) and the lane's own values k and
+// k ^ 2^(b-2) for b >= 2.  Each butterfly forms u + v and u - v, u the element
+// with the lower coordinate; x stages first, then y.
+template <typename T, int B>
+__device__ __forceinline__ T lane_partner(T v) {
+  if constexpr (B < 4) return xor_lane<(1 << B)>(v);
+  else return __shfl_xor(v, 1 << B, 64);
+}
+
+template <typename T, int B>
+__device__ __forceinline__ void butterfly_lanes(T (&v)[4], int lane) {
+  const bool upper = (lane >> B) & 1;
 #pragma unroll
-  for (int b = 0; b < L; ++b) {
-    if (t < 128) {
-      const int row = t >> 3, pi = t & 7;
-      const int xa = ((pi >> b) << (b + 1)) | (pi & ((1 << b) - 1)), xb = xa | (1 << b);
-      const T u = tile[row][xa], v = tile[row][xb];
-      tile[row][xa] = u + v;
-      tile[row][xb] = u - v;
-    }
-    __syncthreads();
-  }
-#pragma unroll
-  for (int b = 0; b < L; ++b) {
-    if (t < 128) {
-      const int col = t & 15, pi = t >> 4;
-      const int ya = ((pi >> b) << (b + 1)) | (pi & ((1 << b) - 1)), yb = ya | (1 << b);
-      const T u = tile[ya][col], v = tile[yb][col];
-      tile[ya][col] = u + v;
-      tile[yb][col] = u - v;
-    }
-    __syncthreads();
+  for (int k = 0; k < 4; ++k) {
+    const T p = lane_partner<T, B>(v[k]);
+    v[k] = upper ? p - v[k] : v[k] + p;
   }
 }
 
-// z = H^T diag(4^-L / (d + lambda)) H s on the 16 x 16 tile, in place
-// (1/0 := 0).  Threads t < 256 own pixel (t & 15, t >> 4) and pass that
-// pixel's d + lambda (0 outside the image).
-template <typename T, int L>
-__device__ __forceinline__ void wmg_tile(T (*tile)[kTile + 1], double dl) {
-  wht16<T, L>(tile);
-  const int t = threadIdx.x;
-  if (t < kTile * kTile) {
-    const int px = t & (kTile - 1), py = t / kTile;
-    const double inv = dl != 0.0 ? (1.0 / (double)(1u << (2 * L))) / dl : 0.0;
-    tile[py][px] = (T)((double)tile[py][px] * inv);
+template <typename T, int B>
+__device__ __forceinline__ void butterfly_regs(T (&v)[4]) {
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    if (k & (1 << B)) continue;
+    const T u = v[k], w = v[k | (1 << B)];
+    v[k] = u + w;
+    v[k | (1 << B)] = u - w;
   }
-  __syncthreads();
-  wht16<T, L>(tile);
+}
+
+template <typename T, int L>
+__device__ __forceinline__ void wht_wave(T (&v)[4], int lane) {
+  if constexpr (L > 0) butterfly_lanes<T, 0>(v, lane);
+  if constexpr (L > 1) butterfly_lanes<T, 1>(v, lane);
+  if constexpr (L > 2) butterfly_lanes<T, 2>(v, lane);
+  if constexpr (L > 3) butterfly_lanes<T, 3>(v, lane);
+  if constexpr (L > 0) butterfly_lanes<T, 4>(v, lane);
+  if constexpr (L > 1) butterfly_lanes<T, 5>(v, lane);
+  if constexpr (L > 2) butterfly_regs<T, 0>(v);
+  if constexpr (L > 3) butterfly_regs<T, 1>(v);
+}
+
+// dl[k]: d + lambda of the lane's pixel k (0 outside the image).
+template <typename T, int L>
+__device__ __forceinline__ void wmg_wave(T (&v)[4], const double (&dl)[4], int lane) {
+  wht_wave<T, L>(v, lane);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const double inv = dl[k] != 0.0 ? (1.0 / (double)(1u << (2 * L))) / dl[k] : 0.0;
+    v[k] = (T)((double)v[k] * inv);
+  }
+  wht_wave<T, L>(v, lane);
 }
 
 // Angle groups per block: group g handles the chunks c = g, g + G, ...; the G
@@ -432,33 +444,60 @@ __device__ __forceinline__ void backward_body(const BwdK<T>& a, const BlockPos p
     __syncthreads();
   }
   set_priority(3);
-  // CGLS: issue the epilogue's global loads before the partial-sum barrier
+  // The records fetched ahead end with the loop (no load into them is still
+  // in flight here); taking them now keeps the compiler from waiting on the
+  // epilogue's loads when it reuses their registers.
+#pragma unroll
+  for (int i = 0; i < Raw<T>::kWords; ++i) asm volatile("" ::"v"(ahead.w[i]));
+  // CGLS: issue the epilogue's loads before the partial-sum barrier, as
+  // buffer loads (pixels outside the image read 0, so no load is predicated
+  // and nothing that uses them is pulled ahead of the barrier)
   T z_in[2] = {T(0), T(0)}, p_in[2] = {T(0), T(0)}, x_in[2] = {T(0), T(0)};
-  double d_own = 0.0;   // d + lambda of the WMG pixel of threads < 256
+  T d_raw[4] = {T(0), T(0), T(0), T(0)};   // d of the first wave's WMG pixels
   if constexpr (MODE == BWD_CGLS || MODE == BWD_CGLS_INIT) {
+    const size_t img_bytes = (size_t)n * n * sizeof(T);
     if (grp == 0) {
+      const __amdgpu_buffer_rsrc_t rx = buffer_rsrc(a.xo, img_bytes);
 #pragma unroll
       for (int q = 0; q < 2; ++q) {
         const int iy = q ? iy1 : iy0;
-        if (ix < n && iy < n) {
-          const size_t px = (size_t)iy * n + ix;
-          if constexpr (MODE == BWD_CGLS) {
-            z_in[q] = a.zP[(size_t)iy * a.ld + ix + kPad];
-            p_in[q] = a.p[px];
-          }
-          x_in[q] = a.xo[px];
+        const bool in = ix < n && iy < n;
+        const unsigned off = in ? (unsigned)(iy * n + ix) * (unsigned)sizeof(T) : kOutside;
+        if constexpr (MODE == BWD_CGLS) {
+          const __amdgpu_buffer_rsrc_t rz = buffer_rsrc(a.zP, (size_t)n * a.ld * sizeof(T));
+          const __amdgpu_buffer_rsrc_t rp = buffer_rsrc(a.p, img_bytes);
+          const unsigned offz =
+              in ? (unsigned)(iy * a.ld + ix + kPad) * (unsigned)sizeof(T) : kOutside;
+          z_in[q] = load_elem(rz, offz, 0, T(0));
+          p_in[q] = load_elem(rp, off, 0, T(0));
         }
+        x_in[q] = load_elem(rx, off, 0, T(0));
       }
     }
     const int tt = threadIdx.x;
-    if (a.fuse && !a.identity && tt < kTile * kTile) {
-      const int ix2 = pos.x * kTile + (tt & (kTile - 1)), iy2 = pos.y * kTile + tt / kTile;
-      if (ix2 < n && iy2 < n) d_own = (double)a.d[(size_t)iy2 * n + ix2] + a.st->lambda;
+    if (a.fuse && !a.identity && tt < 64) {
+      const __amdgpu_buffer_rsrc_t rd = buffer_rsrc(a.d, img_bytes);
+      const int ix2 = pos.x * kTile + (tt & (kTile - 1));
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int iy2 = pos.y * kTile + (tt >> 4) + 4 * k;
+        const unsigned off =
+            ix2 < n && iy2 < n ? (unsigned)(iy2 * n + ix2) * (unsigned)sizeof(T) : kOutside;
+        d_raw[k] = load_elem(rd, off, 0, T(0));
+      }
     }
   }
   part[grp][0][t] = acc0;
   part[grp][1][t] = acc1;
   __syncthreads();
+  if constexpr (MODE == BWD_CGLS || MODE == BWD_CGLS_INIT) {
+    // first uses of the epilogue's loads here, after the barrier (otherwise
+    // their conversions are placed, with a wait, right after the loads)
+#pragma unroll
+    for (int q = 0; q < 2; ++q) asm volatile("" : "+v"(z_in[q]), "+v"(p_in[q]), "+v"(x_in[q]));
+#pragma unroll
+    for (int k = 0; k < 4; ++k) asm volatile("" : "+v"(d_raw[k]));
+  }
   double bp[2] = {0.0, 0.0};
   if (grp == 0) {
 #pragma unroll
@@ -517,33 +556,47 @@ __device__ __forceinline__ void backward_body(const BwdK<T>& a, const BlockPos p
     }
     if (!a.fuse) return;   // uniform: the WMG apply runs as its own launch
     __syncthreads();
+    // the first wave: the WMG apply on the whole tile and the four dot
+    // products (its lanes' pixels in order k, then the block sum)
     const int tt = threadIdx.x;
     const int qx = tt & (kTile - 1), qy = tt / kTile;   // pixel of threads tt < 256
-    T s_own = T(0), p_own = T(0);
-    if (tt < kTile * kTile) {
-      s_own = stile[qy][qx];
-      p_own = ptile[qy][qx];
-    }
-    __syncthreads();
-    if (!a.identity) {
-      switch (a.L) {
-        case 0: wmg_tile<T, 0>(stile, d_own); break;
-        case 1: wmg_tile<T, 1>(stile, d_own); break;
-        case 2: wmg_tile<T, 2>(stile, d_own); break;
-        case 3: wmg_tile<T, 3>(stile, d_own); break;
-        default: wmg_tile<T, 4>(stile, d_own); break;
+    double v[4] = {0.0, 0.0, 0.0, 0.0};   // <s,z>, ||s||^2, ||z||^2, <z,p>
+    if (tt < 64) {
+      // d + lambda of the lane's pixels, 0 outside the image
+      double dl[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const bool in = x0 + qx < n && y0 + (tt >> 4) + 4 * k < n;
+        dl[k] = in ? (double)d_raw[k] + lambda : 0.0;
+      }
+      T sv[4], zv[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) zv[k] = sv[k] = stile[(tt >> 4) + 4 * k][qx];
+      if (!a.identity) {
+        switch (a.L) {
+          case 0: wmg_wave<T, 0>(zv, dl, tt); break;
+          case 1: wmg_wave<T, 1>(zv, dl, tt); break;
+          case 2: wmg_wave<T, 2>(zv, dl, tt); break;
+          case 3: wmg_wave<T, 3>(zv, dl, tt); break;
+          default: wmg_wave<T, 4>(zv, dl, tt); break;
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int ly = (tt >> 4) + 4 * k;
+        const double sd = (double)sv[k], zd = (double)zv[k];
+        v[0] += sd * zd;
+        v[1] += sd * sd;
+        v[2] += zd * zd;
+        if (MODE == BWD_CGLS && lambda != 0.0) v[3] += zd * (double)ptile[ly][qx];
+        stile[ly][qx] = zv[k];
       }
     }
-    double v[4] = {0.0, 0.0, 0.0, 0.0};   // <s,z>, ||s||^2, ||z||^2, <z,p>
+    __syncthreads();
     T z = T(0), zt = T(0);
     if (tt < kTile * kTile) {
       z = stile[qy][qx];
       zt = stile[qx][qy];
-      const double sd = (double)s_own, zd = (double)z;
-      v[0] = sd * zd;
-      v[1] = sd * sd;
-      v[2] = zd * zd;
-      if (MODE == BWD_CGLS && lambda != 0.0) v[3] = zd * (double)p_own;
     }
     SolverState* sst = a.st;
     reduce_to_finisher<4, kThreads * G / 64>(v, a.slots, pos.count(), pos.id(),

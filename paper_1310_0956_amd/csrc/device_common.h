@@ -219,11 +219,14 @@ __device__ __forceinline__ void reduce_to_finisher(double (&v)[W], double* __res
       unsigned long long u[kBatch][W];
 #pragma unroll
       for (int k = 0; k < kBatch; ++k) {
+        // batch entries past the last block for the whole wave are not loaded
+        const bool wave_in = __builtin_amdgcn_readfirstlane(b0 + k * kStride) < nblocks;
         const int b = min(b0 + k * kStride, nblocks - 1);
 #pragma unroll
         for (int i = 0; i < W; ++i)
-          u[k][i] = __hip_atomic_load(&bits[(size_t)i * nblocks + b], __ATOMIC_RELAXED,
-                                      __HIP_MEMORY_SCOPE_AGENT);
+          u[k][i] = wave_in ? __hip_atomic_load(&bits[(size_t)i * nblocks + b], __ATOMIC_RELAXED,
+                                                __HIP_MEMORY_SCOPE_AGENT)
+                            : kSlotEmpty;
       }
 #pragma unroll
       for (int k = 0; k < kBatch; ++k) {
