@@ -599,12 +599,13 @@ __device__ __forceinline__ void backward_body(const BwdK<T>& a, const BlockPos p
       zt = stile[qx][qy];
     }
     SolverState* sst = a.st;
-    reduce_to_finisher<4, kThreads * G / 64>(v, a.slots, pos.count(), pos.id(),
-                                             [sst, degen](double (&tot)[4], bool late) {
-                                               if (late) sst->done = 4;
-                                               else cgls_precond_finish(sst, tot,
-                                                                        MODE == BWD_CGLS_INIT, degen);
-                                             });
+    // the finisher reads the state fields of the step before its block sum
+    reduce_to_finisher<4, kThreads * G / 64>(
+        v, a.slots, pos.count(), pos.id(), [sst]() { return cgls_scalars(sst); },
+        [sst, degen](double (&tot)[4], bool late, const CglsScalars& sc) {
+          if (late) sst->done = 4;
+          else cgls_precond_finish(sst, sc, tot, MODE == BWD_CGLS_INIT, degen);
+        });
     if constexpr (MODE == BWD_CGLS) {
       if (grp == 0) {
 #pragma unroll

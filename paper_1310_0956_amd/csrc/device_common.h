@@ -188,11 +188,13 @@ __device__ __forceinline__ double load_elem(__amdgpu_buffer_rsrc_t rs, unsigned 
 // waits for hold nothing it needs, so the poll ends; it still gives up after
 // kPollTicks of the 100 MHz constant clock and then passes late = true.
 // Non-finisher blocks return at once: their bulk stores need no ordering.
+// pre() runs in the finisher once the poll is done (loads whose latency
+// then overlaps the block sum); its result is passed to fin.
 constexpr unsigned long long kPollTicks = 1000000000ull;   // 10 s
 
-template <int W, int NW = 4, typename F>
+template <int W, int NW = 4, typename P, typename F>
 __device__ __forceinline__ void reduce_to_finisher(double (&v)[W], double* __restrict__ slots,
-                                                   int nblocks, int block_id, F fin) {
+                                                   int nblocks, int block_id, P pre, F fin) {
   __shared__ double sh[NW * W];
   __shared__ int late;
   if (threadIdx.x == 0) late = 0;
@@ -242,6 +244,7 @@ __device__ __forceinline__ void reduce_to_finisher(double (&v)[W], double* __res
     if (full || __builtin_amdgcn_s_memrealtime() - t0 > kPollTicks) break;
     __builtin_amdgcn_s_sleep(8);
   }
+  const auto snap = pre();
   if (!full) late = 1;
   for (int b = threadIdx.x; b < nblocks; b += NW * 64) {
 #pragma unroll
@@ -250,7 +253,7 @@ __device__ __forceinline__ void reduce_to_finisher(double (&v)[W], double* __res
                          __HIP_MEMORY_SCOPE_AGENT);
   }
   block_sum<W, NW>(acc, sh);
-  if (threadIdx.x == 0) fin(acc, late != 0);
+  if (threadIdx.x == 0) fin(acc, late != 0, snap);
 }
 
 __device__ __forceinline__ bool finite(double v) { return __builtin_isfinite(v); }
@@ -267,8 +270,20 @@ __device__ __forceinline__ bool finite(double v) { return __builtin_isfinite(v);
 __device__ __forceinline__ int cgls_degenerate(double delta) {
   return !finite(delta) ? 3 : (delta <= 0.0 ? 1 : 0);
 }
-__device__ __forceinline__ void cgls_precond_finish(SolverState* st, const double (&t)[4],
-                                                    bool init, int degen = 0) {
+// The state fields the step reads, taken ahead of the totals (a finisher
+// loads them before it polls, off the end of the launch's critical path).
+struct CglsScalars {
+  double gamma, pp, s0, tol;
+  int iter, max_iter, fixed, hist_cap;
+  double* hist;
+};
+__device__ __forceinline__ CglsScalars cgls_scalars(const SolverState* st) {
+  return CglsScalars{st->gamma, st->pp,       st->s0,    st->tol, st->iter,
+                     st->max_iter, st->fixed, st->hist_cap, st->hist};
+}
+__device__ __forceinline__ void cgls_precond_finish(SolverState* st, const CglsScalars& c,
+                                                    const double (&t)[4], bool init,
+                                                    int degen = 0) {
   if (degen) {
     st->done = degen;
     return;
@@ -281,24 +296,30 @@ __device__ __forceinline__ void cgls_precond_finish(SolverState* st, const doubl
     st->relres = 1.0;
     st->iter = 0;
     st->init = 1;
-    if (!finite(st->s0) || !finite(t[0])) st->done = 3;
-    else if (st->s0 == 0.0) { st->done = 1; st->relres = 0.0; }
+    const double s0 = sqrt(t[1]);
+    if (!finite(s0) || !finite(t[0])) st->done = 3;
+    else if (s0 == 0.0) { st->done = 1; st->relres = 0.0; }
     return;
   }
   const double g = t[0];
-  const double beta = g / st->gamma;
-  st->pp = t[2] + 2.0 * beta * t[3] + beta * beta * st->pp;
+  const double beta = g / c.gamma;
+  st->pp = t[2] + 2.0 * beta * t[3] + beta * beta * c.pp;
   st->beta = beta;
   st->gamma = g;
-  st->iter += 1;
-  const double rr = sqrt(t[1]) / st->s0;
+  const int iter = c.iter + 1;
+  st->iter = iter;
+  const double rr = sqrt(t[1]) / c.s0;
   st->relres = rr;
-  if (st->hist && st->iter <= st->hist_cap) st->hist[st->iter - 1] = rr;
+  if (c.hist && iter <= c.hist_cap) c.hist[iter - 1] = rr;
   if (!finite(rr) || !finite(beta)) st->done = 3;
-  else if (st->fixed) { if (st->iter >= st->max_iter) st->done = 1; }
-  else if (rr <= st->tol) st->done = 1;
-  else if (st->iter >= st->max_iter) st->done = 2;
+  else if (c.fixed) { if (iter >= c.max_iter) st->done = 1; }
+  else if (rr <= c.tol) st->done = 1;
+  else if (iter >= c.max_iter) st->done = 2;
   else if (g == 0.0) st->done = 1;
+}
+__device__ __forceinline__ void cgls_precond_finish(SolverState* st, const double (&t)[4],
+                                                    bool init, int degen = 0) {
+  cgls_precond_finish(st, cgls_scalars(st), t, init, degen);
 }
 
 // Wave issue priority 0..3 (higher issues first; equal priorities issue
