@@ -20,14 +20,28 @@ K M^-1 u = f with f = W^T b, x = M^-1 u, Arnoldi with modified Gram-Schmidt and
 Givens rotations; residual estimate |g_{j+1}| / ||f||.  One matvec = one W and
 one W^T application.
 
+BiCGStab, right preconditioned (the paper's primary Krylov solver, Section
+2.3.1, on the normal equations with A = W^T W (+ lam I) and f = W^T b, right
+preconditioning as in eq. sys_prec): van der Vorst's recursion with shadow
+vector rhat = r_0 = f, x_0 = 0,
+    rho = <rhat, r>;  beta = (rho / rho_prev) (alpha / omega)
+    p = r + beta (p - omega v);  phat = M^-1 p;  v = K phat
+    alpha = rho / <rhat, v>;  s = r - alpha v
+    shat = M^-1 s;  t = K shat;  omega = <t, s> / <t, t>   (0 when t = 0)
+    x += alpha phat + omega shat;  r = s - omega t
+relres = ||r|| / ||r_0||; two matvecs per iteration.  The paper does not give
+the variant: this is the textbook one (reading listed in the design notes).
+
 SIRT (eq. sys_sirt, eq. sirt_it): R = inverse row sums, C = inverse column
 sums (0 where a sum is 0), x <- x + C W^T R (b - W x); relres is
 ||C W^T R (b - W x_k)|| / ||C W^T R b||.
 
 Parity status: PCGLS pinned by the Krylov-subspace minimisation property and
 dense least squares on tiny systems; GMRES by brute-force minimisation over
-the Krylov space and exact solve with restart >= N; SIRT by the closed form
-x_k = sum_{i<k} S^i C W^T R b.
+the Krylov space and exact solve with restart >= N; BiCGStab by the step
+properties (<rhat, s> = 0, r orthogonal to t), the recursive residual equal
+to the true one, convergence to the dense solve and a one-step solve with the
+exact preconditioner; SIRT by the closed form x_k = sum_{i<k} S^i C W^T R b.
 """
 from __future__ import annotations
 
@@ -170,6 +184,72 @@ def gmres_right(W, b, tol=1e-3, restart=30, max_iter=1000, lam=0.0, precond=None
             r = f - K(x)                          # true residual at restart
             matvecs += 1
     return Result(x, total, matvecs, relres, hist, converged)
+
+
+def bicgstab_right(W, b, tol=1e-3, max_iter=1000, lam=0.0, precond=None, fixed_iters=None,
+                   callback=None) -> Result:
+    """Right-preconditioned BiCGStab on (W^T W + lam I) M^-1 u = W^T b, x = M^-1 u.
+
+    Stops when ||r|| / ||r_0|| <= tol (not with fixed_iters), after max_iter
+    iterations, or at a breakdown (rho = 0 or <rhat, v> = 0; converged stays
+    False).  callback(i, vectors), if given, receives after iteration i a dict
+    of that iteration's rhat, r_prev, p, phat, v, s, shat, t, x, r and the
+    scalars alpha, omega, rho."""
+    Minv = precond or _identity
+
+    def K(v):
+        return W.T @ (W @ v) + lam * v
+
+    b = np.asarray(b, dtype=np.float64).ravel()
+    N = W.shape[1]
+    f = W.T @ b
+    r = f.copy()
+    r0norm = float(np.linalg.norm(r))
+    x = np.zeros(N)
+    hist = []
+    if r0norm == 0.0:
+        return Result(x, 0, 0, 0.0, hist, True)
+    rhat = r.copy()
+    p = np.zeros(N)
+    v = np.zeros(N)
+    rho_prev = alpha = omega = 1.0
+    limit = fixed_iters if fixed_iters is not None else max_iter
+    relres = 1.0
+    converged = False
+    it = 0
+    while it < limit:
+        rho = float(rhat @ r)
+        if rho == 0.0 or not np.isfinite(rho):
+            break
+        beta = (rho / rho_prev) * (alpha / omega)
+        p = r + beta * (p - omega * v)
+        phat = Minv(p)
+        v = K(phat)
+        rv = float(rhat @ v)
+        if rv == 0.0 or not np.isfinite(rv):
+            break
+        alpha = rho / rv
+        s = r - alpha * v
+        shat = Minv(s)
+        t = K(shat)
+        tt = float(t @ t)
+        omega = float(t @ s) / tt if tt != 0.0 else 0.0
+        r_prev = r
+        x = x + alpha * phat + omega * shat
+        r = s - omega * t
+        rho_prev = rho
+        it += 1
+        relres = float(np.linalg.norm(r)) / r0norm
+        hist.append(relres)
+        if callback is not None:
+            callback(it, dict(rhat=rhat, r_prev=r_prev, p=p, phat=phat, v=v, s=s, shat=shat, t=t,
+                              x=x, r=r, alpha=alpha, omega=omega, rho=rho))
+        if fixed_iters is None and relres <= tol:
+            converged = True
+            break
+        if omega == 0.0:
+            break
+    return Result(x, it, 2 * it, relres, hist, converged)
 
 
 def sirt_weights(W):

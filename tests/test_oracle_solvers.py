@@ -5,7 +5,11 @@
     dense least-squares solve); the converged iterate equals numpy lstsq;
   * GMRES iterate k minimises ||f - K M^-1 u|| over u in span{(K M^-1)^i f, i < k};
     with restart >= N it returns K^-1 f;
-  * SIRT iterate k equals sum_{i<k} S^i C W^T R b with S = I - C W^T R W.
+  * SIRT iterate k equals sum_{i<k} S^i C W^T R b with S = I - C W^T R W;
+  * BiCGStab: each step makes s Petrov-Galerkin orthogonal to the shadow vector
+    (<rhat, s> = 0) and r = s - omega t orthogonal to t (omega minimises ||s - omega t||);
+    the recursive residual equals f - K x; the iterates converge to the dense solve;
+    with the exact preconditioner M^-1 = K^-1 one step solves the system.
 """
 import numpy as np
 import pytest
@@ -124,3 +128,59 @@ def test_sirt_zero_rows_get_zero_weight():
     rs = np.asarray(W.sum(axis=1)).ravel()
     assert (rs == 0).any()
     assert (R[rs == 0] == 0).all() and (R[rs > 0] > 0).all()
+
+
+def _prec(g, W, use_prec, L=1):
+    if not use_prec:
+        return None
+    d = wmg.packet_diagonal(W, g.n, L)
+    return lambda v: wmg.apply_additive_diag(v, d, L)  # noqa: E731
+
+
+@pytest.mark.parametrize("lam,use_prec", [(0.0, False), (0.0, True), (0.3, True)])
+def test_bicgstab_step_properties_and_true_residual(lam, use_prec):
+    g, W, b = _tiny()
+    Wd = W.toarray()
+    K = Wd.T @ Wd + lam * np.eye(g.N)
+    f = Wd.T @ b
+    seen = []
+
+    def cb(i, v):
+        sc = np.linalg.norm(v["rhat"]) * np.linalg.norm(v["s"])
+        assert abs(v["rhat"] @ v["s"]) <= 1e-9 * sc
+        if v["omega"] != 0.0:
+            assert abs(v["r"] @ v["t"]) <= 1e-9 * np.linalg.norm(v["r"]) * np.linalg.norm(v["t"])
+            # omega minimises ||s - w t||: nearby values do no better
+            for dw in (1e-3, -1e-3):
+                assert np.linalg.norm(v["s"] - (v["omega"] + dw) * v["t"]) >= np.linalg.norm(v["r"])
+        true_r = f - K @ v["x"]
+        assert np.linalg.norm(v["r"] - true_r) <= 1e-9 * np.linalg.norm(f)
+        seen.append(i)
+
+    res = solvers.bicgstab_right(W, b, lam=lam, precond=_prec(g, W, use_prec), fixed_iters=8,
+                                 callback=cb)
+    assert seen == list(range(1, res.iters + 1)) and res.iters >= 6
+    for k, rr in enumerate(res.history):
+        assert rr >= 0.0
+
+
+@pytest.mark.parametrize("lam,use_prec", [(0.0, False), (0.0, True), (0.3, True)])
+def test_bicgstab_converges_to_dense_solve(lam, use_prec):
+    g, W, b = _tiny()
+    Wd = W.toarray()
+    K = Wd.T @ Wd + lam * np.eye(g.N)
+    want = np.linalg.solve(K, Wd.T @ b)
+    res = solvers.bicgstab_right(W, b, tol=1e-12, max_iter=2000, lam=lam,
+                                 precond=_prec(g, W, use_prec))
+    assert res.converged and res.matvecs == 2 * res.iters
+    assert np.linalg.norm(res.x - want) <= 1e-7 * np.linalg.norm(want)
+
+
+def test_bicgstab_exact_preconditioner_solves_in_one_step():
+    g, W, b = _tiny(n=4, m=12, nb=6)
+    Wd = W.toarray()
+    K = Wd.T @ Wd + 0.1 * np.eye(g.N)
+    Kinv = np.linalg.inv(K)
+    res = solvers.bicgstab_right(W, b, tol=1e-10, max_iter=5, lam=0.1, precond=lambda v: Kinv @ v)
+    assert res.converged and res.iters == 1
+    assert np.linalg.norm(res.x - Kinv @ (Wd.T @ b)) <= 1e-10 * np.linalg.norm(res.x)
