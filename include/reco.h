@@ -168,6 +168,17 @@ reco_status reco_solve_gmres(reco_geometry g, const void* b, void* x,
                              const reco_solve_opts* opts, reco_solve_info* info,
                              void* stream);
 
+/* BiCGStab (the paper's primary Krylov solver, Section 2.3.1), right
+ * preconditioned on (W^T W + lambda I) M^-1 u = W^T b, x = M^-1 u (eq.
+ * sys_prec): van der Vorst's recursion with shadow vector r_0 = W^T b,
+ * relres = ||r_k|| / ||r_0||, two matvecs (W and W^T each) per iteration.
+ * opts->restart is ignored.  A breakdown (rho = 0, <r_0, v> = 0, or omega = 0
+ * before tol is met) returns RECO_ENOTCONV with x = the last iterate.
+ * Otherwise as reco_solve_cgls. */
+reco_status reco_solve_bicgstab(reco_geometry g, const void* b, void* x,
+                                const reco_solve_opts* opts, reco_solve_info* info,
+                                void* stream);
+
 /* SIRT, x <- x + C W^T R (b - W x) with R, C the inverse row and column sums
  * of W (eq. sys_sirt, eq. sirt_it; 1/0 := 0).  lambda and precond are
  * ignored.  Otherwise as reco_solve_cgls. */

@@ -63,6 +63,7 @@ _sig = {
     "reco_wmg_apply": (_S, [_P, _P, _P, C.c_double, _P]),
     "reco_solve_cgls": (_S, [_P, _P, _P, C.POINTER(SolveOpts), C.POINTER(SolveInfo), _P]),
     "reco_solve_gmres": (_S, [_P, _P, _P, C.POINTER(SolveOpts), C.POINTER(SolveInfo), _P]),
+    "reco_solve_bicgstab": (_S, [_P, _P, _P, C.POINTER(SolveOpts), C.POINTER(SolveInfo), _P]),
     "reco_solve_sirt": (_S, [_P, _P, _P, C.POINTER(SolveOpts), C.POINTER(SolveInfo), _P]),
     "reco_solve_batch": (_S, [_S, C.POINTER(_P), C.POINTER(_P), C.POINTER(_P),
                               C.POINTER(SolveOpts), C.POINTER(SolveInfo), _P]),
@@ -260,6 +261,11 @@ class Geometry:
     def solve_gmres(self, b, x=None, tol=1e-3, max_iter=1000, lam=0.0, precond=PRECOND_WMG,
                     restart=30, fixed_iters=0, history=False, check_every=0, stream=None):
         return self._solve(_lib.reco_solve_gmres, b, x, tol, max_iter, lam, precond, restart,
+                           fixed_iters, history, check_every, stream)
+
+    def solve_bicgstab(self, b, x=None, tol=1e-3, max_iter=1000, lam=0.0, precond=PRECOND_WMG,
+                       fixed_iters=0, history=False, check_every=0, stream=None):
+        return self._solve(_lib.reco_solve_bicgstab, b, x, tol, max_iter, lam, precond, 30,
                            fixed_iters, history, check_every, stream)
 
     def solve_sirt(self, b, x=None, tol=1e-3, max_iter=1000, fixed_iters=0, history=False,

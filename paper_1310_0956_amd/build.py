@@ -25,6 +25,7 @@ SOURCES = [
     "vec.hip",
     "solve.hip",
     "gmres.hip",
+    "bicgstab.hip",
     "batch.hip",
     "abi.hip",
     "timing.hip",

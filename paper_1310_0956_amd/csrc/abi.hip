@@ -227,6 +227,17 @@ reco_status reco_solve_gmres(reco_geometry gh, const void* b, void* x, const rec
   })
 }
 
+reco_status reco_solve_bicgstab(reco_geometry gh, const void* b, void* x,
+                                const reco_solve_opts* opts, reco_solve_info* info, void* stream) {
+  RECO_GUARD({
+    Geometry* g = G(gh);
+    need(b, "b");
+    need(x, "x");
+    need(opts, "opts");
+    return reco::solve_bicgstab(*g, b, x, *opts, info, S(stream));
+  })
+}
+
 reco_status reco_solve_sirt(reco_geometry gh, const void* b, void* x, const reco_solve_opts* opts,
                             reco_solve_info* info, void* stream) {
   RECO_GUARD({

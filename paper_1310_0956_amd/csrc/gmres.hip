@@ -224,14 +224,17 @@ reco_status gmres_impl(Geometry& g, const void* bvoid, void* xvoid, const reco_s
       fail(RECO_ENOMEM, "GMRES basis allocation failed");
     }
     w.v_cap = R + 1;
+  }
+  const size_t gm_need = lay.count(chunks) + 8;
+  if (!w.gm || w.gm_cap < gm_need) {
     if (w.gm) (void)hipFree(w.gm);
     w.gm = nullptr;
-  }
-  if (!w.gm) {
-    if (hipMalloc((void**)&w.gm, sizeof(double) * lay.count(chunks) + 64) != hipSuccess) {
+    w.gm_cap = 0;
+    if (hipMalloc((void**)&w.gm, sizeof(double) * gm_need) != hipSuccess) {
       (void)hipGetLastError();
       fail(RECO_ENOMEM, "GMRES scratch allocation failed");
     }
+    w.gm_cap = gm_need;
   }
   T* V = (T*)w.V;
   T* x = (T*)xvoid;

@@ -25,7 +25,8 @@ struct Workspace {
   int hist_cap = 0;
   void* V = nullptr;                          // GMRES basis [(restart+1) x N]
   int v_cap = 0;                              // vectors allocated in V
-  double* gm = nullptr;                       // GMRES small dense data
+  double* gm = nullptr;                       // GMRES / BiCGStab small dense data
+  size_t gm_cap = 0;                          // doubles allocated in gm
   ~Workspace();
 };
 
@@ -50,6 +51,8 @@ reco_status solve_cgls(Geometry& g, const void* b, void* x, const reco_solve_opt
                        reco_solve_info* info, hipStream_t st);
 reco_status solve_sirt(Geometry& g, const void* b, void* x, const reco_solve_opts& o,
                        reco_solve_info* info, hipStream_t st);
+reco_status solve_bicgstab(Geometry& g, const void* b, void* x, const reco_solve_opts& o,
+                           reco_solve_info* info, hipStream_t st);
 reco_status solve_gmres(Geometry& g, const void* b, void* x, const reco_solve_opts& o,
                         reco_solve_info* info, hipStream_t st);
 
