@@ -399,13 +399,15 @@ def serve_leg(reco, torch, args):
 
 
 def solvers_leg(reco, torch, g, sinos):
-    """The four solvers of the 512^2 workload to rel-res 1e-3 (iteration cap
-    1000): iterations, applications of W^T W and time per reconstruction."""
+    """The solvers of the 512^2 workload to rel-res 1e-3 (iteration cap 1000):
+    iterations, applications of W^T W and time per reconstruction."""
     out = {}
     x = g.new_image()
     runs = [("cgls", lambda b: g.solve_cgls(b, x=x, tol=1e-3, precond=reco.PRECOND_NONE)),
             ("wmg_cgls", lambda b: g.solve_cgls(b, x=x, tol=1e-3)),
             ("wmg_gmres30", lambda b: g.solve_gmres(b, x=x, tol=1e-3, restart=30)),
+            ("bicgstab", lambda b: g.solve_bicgstab(b, x=x, tol=1e-3, precond=reco.PRECOND_NONE)),
+            ("wmg_bicgstab", lambda b: g.solve_bicgstab(b, x=x, tol=1e-3)),
             ("sirt", lambda b: g.solve_sirt(b, x=x, tol=1e-3, max_iter=1000))]
     for name, fn in runs:
         fn(sinos[0])
