@@ -248,6 +248,10 @@ void compute_packet_diagonal(Geometry& g, hipStream_t st);
 void launch_fill(void* p, size_t count, bool f64, double value, hipStream_t st);
 void launch_copy(const void* src, void* dst, size_t count, bool f64, hipStream_t st);
 void launch_invert(void* v, size_t count, bool f64, hipStream_t st);
+// CGLS set-up in one launch: state init, x = p = 0 [N], q = 0 and r = b [M].
+void launch_cgls_prepare(SolverState* st, double tol, int max_iter, int fixed, double lambda,
+                         double* hist, int hist_cap, void* x, void* p, void* q, void* r,
+                         const void* b, size_t N, size_t M, bool f64, hipStream_t s);
 void launch_state_init(SolverState* st, double tol, int max_iter, int fixed, double lambda,
                        double* hist, int hist_cap, hipStream_t s);
 

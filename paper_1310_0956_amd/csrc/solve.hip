@@ -262,11 +262,8 @@ void cgls_setup(Geometry& g, Workspace& w, const void* b, void* x, const reco_so
   const bool fixed = o.fixed_iters > 0;
   const int limit = fixed ? o.fixed_iters : o.max_iter;
   ensure_history(w, limit);
-  launch_state_init(w.st, o.tol, limit, fixed ? 1 : 0, o.lambda, w.hist, limit, st);
-  launch_fill(x, g.N(), g.f64, 0.0, st);
-  launch_fill(w.p, g.N(), g.f64, 0.0, st);
-  launch_fill(w.q, g.M(), g.f64, 0.0, st);
-  launch_copy(b, w.r, g.M(), g.f64, st);
+  launch_cgls_prepare(w.st, o.tol, limit, fixed ? 1 : 0, o.lambda, w.hist, limit, x, w.p, w.q, w.r,
+                      b, g.N(), g.M(), g.f64, st);
   launch_backward(g, BWD_CGLS_INIT, cgls_bwd_args(g, w, x, o), st);
   if (!backward_fuses_wmg(g)) launch_wmg(g, WMG_CGLS_INIT, cgls_wmg_args(w, o), st);
 }

@@ -81,6 +81,37 @@ __global__ void k_state_init(SolverState* st, double tol, int max_iter, int fixe
   *st = s;
 }
 
+// CGLS set-up in one launch: the solver state, x = p = 0, q = 0, r = b.
+template <typename T>
+__global__ __launch_bounds__(256) void k_cgls_prepare(SolverState* st, double tol, int max_iter,
+                                                      int fixed, double lambda, double* hist,
+                                                      int hist_cap, T* __restrict__ x,
+                                                      T* __restrict__ p, T* __restrict__ q,
+                                                      T* __restrict__ r, const T* __restrict__ b,
+                                                      size_t N, size_t M) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    SolverState s{};
+    s.tol = tol;
+    s.max_iter = max_iter;
+    s.fixed = fixed;
+    s.lambda = lambda;
+    s.hist = hist;
+    s.hist_cap = hist_cap;
+    *st = s;
+  }
+  const size_t n = N > M ? N : M;
+  for (size_t i = blockIdx.x * (size_t)256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) {
+    if (i < N) {
+      x[i] = T(0);
+      p[i] = T(0);
+    }
+    if (i < M) {
+      q[i] = T(0);
+      r[i] = b[i];
+    }
+  }
+}
+
 unsigned grid_for(size_t count) {
   size_t b = (count + 255) / 256;
   return (unsigned)(b > 65536 ? 65536 : (b == 0 ? 1 : b));
@@ -141,6 +172,21 @@ void launch_init_batch(const DevTable& t, hipStream_t st) {
   if (t.count == 0) return;
   hipLaunchKernelGGL(k_init_batch, dim3(t.total_blocks), dim3(256), 0, st,
                      (const InitK*)t.args, t.start, t.gx, t.count);
+  HIP_CHECK(hipGetLastError());
+}
+
+void launch_cgls_prepare(SolverState* st, double tol, int max_iter, int fixed, double lambda,
+                         double* hist, int hist_cap, void* x, void* p, void* q, void* r,
+                         const void* b, size_t N, size_t M, bool f64, hipStream_t s) {
+  const unsigned grid = grid_for(N > M ? N : M);
+  if (f64)
+    hipLaunchKernelGGL(k_cgls_prepare<double>, dim3(grid), dim3(256), 0, s, st, tol, max_iter,
+                       fixed, lambda, hist, hist_cap, (double*)x, (double*)p, (double*)q,
+                       (double*)r, (const double*)b, N, M);
+  else
+    hipLaunchKernelGGL(k_cgls_prepare<float>, dim3(grid), dim3(256), 0, s, st, tol, max_iter,
+                       fixed, lambda, hist, hist_cap, (float*)x, (float*)p, (float*)q, (float*)r,
+                       (const float*)b, N, M);
   HIP_CHECK(hipGetLastError());
 }
 
