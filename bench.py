@@ -55,6 +55,8 @@ def parse():
                     help="budget of one more run at 0.7 of saturation (0: skip)")
     ap.add_argument("--serve-slots", type=int, default=64)
     ap.add_argument("--no-tiny64", action="store_true", help="skip the 64^2 float64 leg")
+    ap.add_argument("--no-semiconv", action="store_true",
+                    help="skip the 160^2 noisy-data semi-convergence leg")
     ap.add_argument("--no-ct2048", action="store_true", help="skip the 2048^2 leg")
     ap.add_argument("--no-solvers", action="store_true",
                     help="skip the 512^2 solver comparison (CGLS, GMRES, SIRT)")
@@ -423,6 +425,63 @@ def solvers_leg(reco, torch, g, sinos):
     return out
 
 
+SEMICONV_GRIDS = {
+    "sirt": [1, 2, 5, 10, 20, 50, 100, 200, 300, 500, 700, 1000, 1500, 2000, 3000, 4000, 6000],
+    "bicgstab": [1, 2, 3, 5, 7, 10, 15, 20, 30, 50, 70, 100, 150, 200, 300],
+    "wmg_bicgstab": [1, 2, 3, 4, 5, 6, 8, 10, 12, 14, 17, 20, 25, 30, 40, 60, 100],
+    "wmg_cgls": [1, 2, 3, 4, 5, 6, 8, 10, 12, 14, 17, 20, 25, 30, 40, 60, 100],
+}
+
+
+def semiconv_leg(reco, torch):
+    """The paper's noisy-data experiment (Section 4.3) at its shape: a 160^2
+    image, 400 angles x 160 rays, 3-level WMG, 1% uniform white noise
+    eps = 0.01 U(-1, 1) max|b|; seeded ellipses stand in for its phantom.  For
+    each solver the error ||x_k - x_ex|| / ||x_ex|| (x_0 = 0, so this is
+    ||e_k|| / ||e_0||) on a log-spaced grid of iteration counts, each a
+    separate fixed-iteration solve; k_opt and the error minimum."""
+    import numpy as np
+    import inputs
+    n, m, nb, lv = 160, 400, 160, 3
+    x_ex = inputs.ellipse_phantom(n, 10, 11)
+    g = reco.Geometry(n, m, nb, lv, reco.F32)
+    b = g.project(torch.from_numpy(x_ex.astype(np.float32)).cuda())
+    torch.cuda.synchronize()
+    eps = inputs.uniform_noise(m * nb, 12).reshape(m, nb)
+    bn = b + torch.from_numpy((0.01 * float(b.abs().max()) * eps).astype(np.float32)).cuda()
+    xe = torch.from_numpy(x_ex.astype(np.float32)).cuda()
+    nx = float(torch.linalg.vector_norm(xe))
+    # Tikhonov weight of the paper's regularized Krylov runs, lambda = 10 in its
+    # pixel units; W here measures lengths in units of the domain [-1, 1]^2
+    # (pixel side h = 2/n), so W^T W carries a factor h^2 and so does lambda
+    lam = 10.0 * (2.0 / n) ** 2
+    solve = {"sirt": lambda k: g.solve_sirt(bn, fixed_iters=k),
+             "bicgstab": lambda k: g.solve_bicgstab(bn, fixed_iters=k, precond=reco.PRECOND_NONE),
+             "wmg_bicgstab": lambda k: g.solve_bicgstab(bn, fixed_iters=k),
+             "wmg_cgls": lambda k: g.solve_cgls(bn, fixed_iters=k),
+             "bicgstab_reg": lambda k: g.solve_bicgstab(bn, fixed_iters=k, lam=lam,
+                                                        precond=reco.PRECOND_NONE),
+             "wmg_bicgstab_reg": lambda k: g.solve_bicgstab(bn, fixed_iters=k, lam=lam),
+             "wmg_cgls_reg": lambda k: g.solve_cgls(bn, fixed_iters=k, lam=lam)}
+    out = {"workload": "160^2 image, 400 angles x 160 rays, 10 ellipses, 1% uniform noise, "
+                       "3-level WMG, float32; error of fixed-iteration solves; *_reg: Tikhonov "
+                       f"lambda = 10 h^2 = {lam:.6g}"}
+    grids = dict(SEMICONV_GRIDS)
+    for name in ("bicgstab", "wmg_bicgstab", "wmg_cgls"):
+        grids[name + "_reg"] = SEMICONV_GRIDS[name]
+    for name, ks in grids.items():
+        errs, done = [], []
+        for k in ks:
+            x, info = solve[name](k)
+            errs.append(float(torch.linalg.vector_norm(x - xe)) / nx)
+            done.append(info["iters"])
+        i = int(np.argmin(errs))
+        out[name] = {"k_opt": ks[i], "err_min": round(errs[i], 5),
+                     "curve": [[k, round(e, 5)] for k, e in zip(ks, errs)],
+                     "iters_run": done}
+    return out
+
+
 def tiny64_leg(reco, torch):
     """64^2, 90 angles x 64 bins, 10-ellipse noiseless phantom, float64:
     50 iterations each of SIRT, CGLS and 2-level WMG-CGLS."""
@@ -654,6 +713,9 @@ def main():
         gc.collect()
         torch.cuda.synchronize()
         result["tiny64_f64"] = tiny64_leg(reco, torch)
+    if not args.no_semiconv:
+        progress("semi-convergence 160^2")
+        result["semiconv160"] = semiconv_leg(reco, torch)
     if not args.no_cpu_baseline:
         solved, t_sum, cpu_iters, W = cpu_baseline(args)
         threads = min(16, os.cpu_count() or 1)

@@ -107,6 +107,12 @@ def standard_normal(size: int, seed: int) -> np.ndarray:
     return rng(seed).standard_normal(size)
 
 
+def uniform_noise(size: int, seed: int) -> np.ndarray:
+    """U(-1, 1) draws (float64) for the paper's white-noise model
+    eps = alpha U(-1, 1) max|b| (Section 4.3, eq. noise_term); callers scale them."""
+    return rng(seed).uniform(-1.0, 1.0, size)
+
+
 def default_bins(side: int) -> int:
     """Detector bins of width one pixel covering the image diagonal."""
     return int(math.ceil(side * math.sqrt(2.0)))

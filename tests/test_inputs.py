@@ -44,3 +44,11 @@ def test_workload_mixes_are_seeded():
     assert {r.tol for r in s} <= {1e-2, 1e-3}
     # mean inter-arrival close to 1/rate
     assert abs(s[-1].arrival_s / len(s) - 1 / 20.0) < 0.2 / 20.0
+
+
+def test_uniform_noise_is_seeded_and_in_open_interval():
+    a = inputs.uniform_noise(100000, 12)
+    assert np.array_equal(a, inputs.uniform_noise(100000, 12))
+    assert not np.array_equal(a, inputs.uniform_noise(100000, 13))
+    assert a.min() > -1.0 and a.max() < 1.0
+    assert abs(a.mean()) < 0.01 and abs(a.var() - 1.0 / 3.0) < 0.01
