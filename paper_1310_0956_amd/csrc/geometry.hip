@@ -82,6 +82,7 @@ Geometry::~Geometry() {
   f(d_fwd_rows);
   f(d_fwd_wins);
   f(d_fwd_order);
+  f(d_fwd_blk);
   f(d_bwd);
   f(d_diag64);
   f(d_diag);

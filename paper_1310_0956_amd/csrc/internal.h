@@ -72,6 +72,22 @@ struct Workspace;  // solver buffers (solve.hip)
 // projector (see project.hip).
 constexpr int kPad = 4;
 
+// Everything a forward block needs before its first band, gathered per grid
+// position at setup so that one load brings it: the 64-byte uniform header,
+// then the angle of each of the block's 8 slots (-1 = empty).
+struct FwdBlk {
+  int lb;                  // block g * (bin blocks) + bin block: its rows and band windows
+  int jfirst, jlast;       // bins of the block
+  int lo, hi;              // image rows its rays touch
+  int major;               // walking axis of its angles
+  int k0;                  // first angle (invalid slots shadow it)
+  int nbands;
+  int w0x, w0y, w1x, w1y;  // column windows of the first two bands
+  int pad[4];
+  int k[8];
+};
+static_assert(sizeof(FwdBlk) == 96, "FwdBlk layout");
+
 struct Geometry {
   reco_geometry_desc desc{};
   int n = 0, m = 0, nb = 0, L = 0, T = 1;  // L packet levels, T = 2^L
@@ -86,6 +102,7 @@ struct Geometry {
   void* d_fwd_rows = nullptr;  // [ngroups * bin blocks] row range of each forward block
   void* d_fwd_wins = nullptr;  // [ngroups * bin blocks][fwd_maxb] band column windows
   int* d_fwd_order = nullptr;  // [ngroups * bin blocks] forward block run at each grid position
+  void* d_fwd_blk = nullptr;   // [ngroups * bin blocks] FwdBlk record of each grid position
   int fwd_maxb = 0;
   BwdAngle* d_bwd = nullptr;   // [m]
   std::vector<FwdAngle> h_fwd;

@@ -25,6 +25,7 @@
 // float64 (double path), so the geometry error stays far below the float
 // weight error.
 #include <algorithm>
+#include <cstring>
 #include <vector>
 
 #include "device_common.h"
@@ -57,10 +58,8 @@ struct FwdK {
   const T* b;
   const T* R;
   const FwdAngle* ang;
-  const int* groups;   // [ngroups][8] angle indices, -1 = empty slot
-  const int2* rows;    // [ngroups * nbx] row range of each block
   const int2* wins;    // [ngroups * nbx][maxb] column window of each band
-  const int* order;    // [ngroups * nbx] block (g * nbx + bin block) run at each grid position
+  const FwdBlk* blk;   // [ngroups * nbx] the record of each grid position
   int nbx, maxb;
   SolverState* st;
   RedScratch red;
@@ -311,36 +310,33 @@ __device__ __forceinline__ void forward_body(const FwdK<T>& a, const BlockPos bp
   __shared__ T win[2][BAND * kStride];
   const int t = threadIdx.x;
   const int n = a.n, nb = a.nb;
-  const int lb = a.order[bp.id()];   // block run at this grid position
-  const int g = lb / a.nbx, bx = lb - g * a.nbx;
-  const int jfirst = bx * kBins;
-  const int jlast = min(jfirst + kBins - 1, nb - 1);
-  const int k0 = a.groups[g * kSlots];            // first angle: sets the walk axis
+  // the block's record (setup table, one per grid position): its bins, rows,
+  // walking axis and first band windows, then its angles
+  const FwdBlk* __restrict__ rec = a.blk + bp.id();
+  const int lb = rec->lb;
+  const int jfirst = rec->jfirst, jlast = rec->jlast;
+  const int k0 = rec->k0;            // first angle: sets the walk axis
   // ray of this thread: a wave holds two angles of the group, interleaved by
   // lane parity, so that each half-wave's LDS reads span about 16 bins' worth
   // of columns (fewer bank conflicts than 32 bins of one angle)
-  const int kl = a.groups[g * kSlots + ((t >> 6) << 1) + (t & 1)];
+  const int kl = rec->k[((t >> 6) << 1) + (t & 1)];
   const int jown = jfirst + ((t >> 1) & 31);
   const bool valid = kl >= 0 && jown <= jlast;
   // invalid lanes shadow the block's first ray so that they stay in the window
   const int k = valid ? kl : k0;
   const int j = valid ? jown : jfirst;
   const FwdAngle ang = a.ang[k];
-  const FwdAngle ang0 = a.ang[k0];
-  const T* img = ang0.major ? a.imgTP : a.imgP;
+  const T* img = rec->major ? a.imgTP : a.imgP;
   const __amdgpu_buffer_rsrc_t rs = buffer_rsrc(img, (size_t)n * a.ld * sizeof(T));
-  const double P0 = fma((double)j, ang.inv, ang.A0);
-  // rows the block's rays touch and the column window of each band (setup table)
-  const int blk = lb;
-  const int2 rr = a.rows[blk];
-  const int lo = rr.x, hi = rr.y;
-  const int2* __restrict__ bandwin = a.wins + (size_t)blk * a.maxb;
-  const T B = wB<T>(ang), C = wC<T>(ang), Wm = wM<T>(ang);
-  const float Bq = (float)(-ang.B * 2.3283064365386963e-10), Cq = (float)(ang.C + 0.5 * ang.B);
-  T acc0 = T(0), acc1 = T(0);
-  const int nbands = hi >= lo ? (hi - lo + BAND) / BAND : 0;
-  Walk<T> wk;
-  wk.init(fma((double)lo, ang.slope, P0), ang.slope, ang.dP);
+  // rows the block's rays touch and the column window of each band
+  const int lo = rec->lo, hi = rec->hi;
+  const int nbands = rec->nbands;
+  const int2* __restrict__ bandwin = a.wins + (size_t)lb * a.maxb;
+  // The window of band b + 1 is loaded during band b - 1 (two bands ahead of
+  // its first use, with the opaque zero in its index), so no band waits on
+  // the table; those of bands 0 and 1 come with the record (zeros when absent).
+  Window wcur{rec->w0x, rec->w0y};
+  int2 wahead = make_int2(rec->w1x, rec->w1y);
   // staging: thread loads column (t % kLoadCols) of rows (t / kLoadCols) + kStageRows * i;
   // columns past the window's width are written as zeros (the guard columns);
   // threads with scol >= kStride only idle
@@ -348,31 +344,35 @@ __device__ __forceinline__ void forward_body(const FwdK<T>& a, const BlockPos bp
   const bool stager = scol < kStride;
   const int srow = __builtin_amdgcn_readfirstlane(t / kLoadCols);   // uniform per wave
   const int rbytes = a.ld * (int)sizeof(T);
-  Window wcur{0, 0};
   int cur_shift = 0;   // window start the walker's columns are currently relative to
-  // The window of band b + 1 is loaded during band b - 1 (two bands ahead of
-  // its first use, with the opaque zero in its index), so no band waits on
-  // the table.
-  int2 wahead = make_int2(0, 0);
+  // the table loads above are issued before the stop test (left alone, the
+  // compiler tests first and issues them only after that load returns)
+  asm volatile("" ::: "memory");
   if (__builtin_amdgcn_readfirstlane(done_v)) return;   // before any store and barrier
-  if (nbands > 0) {
-    const int2 w0 = bandwin[0];
-    if (nbands > 1) wahead = bandwin[1];
-    wcur = Window{w0.x, w0.y};
-    if (wcur.c1 - wcur.c0 + 1 <= kWinCols) {
-      // all of the band's loads are issued before the first LDS store
-      T v[STAGE_PER];
+  // the first band's loads, issued before the ray set-up waits for the
+  // angle records
+  const bool first_lds = nbands > 0 && wcur.c1 - wcur.c0 + 1 <= kWinCols;
+  T v0[STAGE_PER];
 #pragma unroll
-      for (int i = 0; i < STAGE_PER; ++i) {
-        const int row = srow + kStageRows * i;
-        v[i] = T(0);
-        if (scol <= wcur.c1 - wcur.c0)
-          v[i] = load_elem(rs, (unsigned)(wcur.c0 + kPad + scol) * sizeof(T), (lo + row) * rbytes,
-                           T(0));
-      }
+  for (int i = 0; i < STAGE_PER; ++i) {
+    const int row = srow + kStageRows * i;
+    v0[i] = T(0);
+    if (first_lds && scol <= wcur.c1 - wcur.c0)
+      v0[i] = load_elem(rs, (unsigned)(wcur.c0 + kPad + scol) * sizeof(T), (lo + row) * rbytes,
+                        T(0));
+  }
+  // the ray: walker and weight coefficients
+  const double P0 = fma((double)j, ang.inv, ang.A0);
+  const T B = wB<T>(ang), C = wC<T>(ang), Wm = wM<T>(ang);
+  const float Bq = (float)(-ang.B * 2.3283064365386963e-10), Cq = (float)(ang.C + 0.5 * ang.B);
+  T acc0 = T(0), acc1 = T(0);
+  Walk<T> wk;
+  wk.init(fma((double)lo, ang.slope, P0), ang.slope, ang.dP);
+  if (nbands > 0) {
+    if (first_lds) {
 #pragma unroll
       for (int i = 0; i < STAGE_PER; ++i)
-        if (stager) win[0][(srow + kStageRows * i) * kStride + scol] = v[i];
+        if (stager) win[0][(srow + kStageRows * i) * kStride + scol] = v0[i];
     }
     __syncthreads();
   }
@@ -544,10 +544,8 @@ FwdK<T> make_args(const Geometry& g, const FwdArgs& a) {
   k.b = (const T*)a.b;
   k.R = (const T*)a.R;
   k.ang = g.d_fwd;
-  k.groups = g.d_groups;
-  k.rows = (const int2*)g.d_fwd_rows;
   k.wins = (const int2*)g.d_fwd_wins;
-  k.order = g.d_fwd_order;
+  k.blk = (const FwdBlk*)g.d_fwd_blk;
   k.part = a.part;
   k.nbx = (g.nb + kBins - 1) / kBins;
   k.maxb = g.fwd_maxb;
@@ -624,6 +622,37 @@ void build_forward_windows(Geometry& g, hipStream_t st) {
     order[pos] = byrows[r];
   }
   HIP_CHECK(hipMemcpyAsync(g.d_fwd_order, order.data(), sizeof(int) * nblk, hipMemcpyHostToDevice,
+                           st));
+  // per grid position: the block's record (its first two band windows from
+  // the table the setup kernel wrote)
+  std::vector<int> groups((size_t)g.ngroups * kSlots);
+  std::vector<int2> wins(nblk * (size_t)g.fwd_maxb);
+  HIP_CHECK(hipMemcpyAsync(groups.data(), g.d_groups, sizeof(int) * groups.size(),
+                           hipMemcpyDeviceToHost, st));
+  HIP_CHECK(hipMemcpyAsync(wins.data(), g.d_fwd_wins, sizeof(int2) * wins.size(),
+                           hipMemcpyDeviceToHost, st));
+  HIP_CHECK(hipStreamSynchronize(st));
+  std::vector<FwdBlk> recs(nblk);
+  for (size_t pos = 0; pos < nblk; ++pos) {
+    const int lb = order[pos];
+    const int gi = lb / nbx, bx = lb - gi * nbx;
+    FwdBlk& r = recs[pos];
+    std::memset(&r, 0, sizeof(r));
+    r.lb = lb;
+    r.jfirst = bx * kBins;
+    r.jlast = std::min(r.jfirst + kBins - 1, g.nb - 1);
+    r.lo = rows[lb].x;
+    r.hi = rows[lb].y;
+    r.nbands = r.hi >= r.lo ? (r.hi - r.lo + band) / band : 0;
+    r.k0 = groups[(size_t)gi * kSlots];
+    r.major = g.h_fwd[r.k0].major;
+    const int2* wb = wins.data() + (size_t)lb * g.fwd_maxb;
+    if (r.nbands > 0) { r.w0x = wb[0].x; r.w0y = wb[0].y; }
+    if (r.nbands > 1) { r.w1x = wb[1].x; r.w1y = wb[1].y; }
+    for (int s = 0; s < kSlots; ++s) r.k[s] = groups[(size_t)gi * kSlots + s];
+  }
+  HIP_CHECK(hipMalloc(&g.d_fwd_blk, sizeof(FwdBlk) * nblk));
+  HIP_CHECK(hipMemcpyAsync(g.d_fwd_blk, recs.data(), sizeof(FwdBlk) * nblk, hipMemcpyHostToDevice,
                            st));
   HIP_CHECK(hipStreamSynchronize(st));
 }
