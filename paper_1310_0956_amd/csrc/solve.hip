@@ -93,7 +93,7 @@ size_t geometry_bytes(const reco_geometry_desc& d) {
   const size_t bands = (size_t)(d.n + 15) / 16;
   const size_t blocks = groups * (size_t)((d.n_bins + 31) / 32);
   return (sizeof(FwdAngle) + sizeof(BwdAngle) + 8 * sizeof(int)) * (size_t)(d.n_angles + 8) +
-         blocks * ((bands + 1) * 8 + 4) + N * (8 + es) + 4096;
+         blocks * ((bands + 1) * 8 + 4 + sizeof(FwdBlk)) + N * (8 + es) + 4096;
 }
 
 void return_workspace(Geometry& g, Workspace* w) {
