@@ -302,6 +302,10 @@ __device__ __forceinline__ void backward_body(const BwdK<T>& a, const BlockPos p
   // they would be waited for before the first angle records are requested).
   int vzero;
   asm volatile("v_mov_b32 %0, 0" : "=v"(vzero));
+  // The prologue (loads, barriers, latency bound) runs at the top wave
+  // priority: blocks that start late would otherwise wait behind the chunk
+  // steps of the blocks already computing, which raise theirs.
+  set_priority(3);
   // solver finished: later launches are no-ops (tested once the prologue's
   // first loads are in flight; the flag is the same for every block, and
   // nothing is stored before the test)

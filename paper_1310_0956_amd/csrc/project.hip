@@ -295,6 +295,9 @@ template <typename T, int MODE>
 __device__ __forceinline__ void forward_body(const FwdK<T>& a, const BlockPos bp) {
   constexpr int BAND = kBand<T>;
   constexpr int STAGE_PER = BAND / kStageRows;   // loads per thread per band
+  // The prologue runs at the top wave priority (latency bound; the band
+  // loop lowers it with the work left).
+  set_priority(3);
   // Loads whose results are wanted later carry an opaque zero held in a
   // vector register: the value then stays in vector registers until it is
   // used, instead of being moved to scalar registers (which would wait for
