@@ -106,6 +106,18 @@ __device__ __forceinline__ void block_sum(double (&v)[W], double* sh) {
   __syncthreads();
 }
 
+// Marks every word of s as read and rewritten here, in vector registers: a
+// value loaded earlier is then first used (and waited for) at this point.
+template <typename S>
+__device__ __forceinline__ void in_vgprs(S& s) {
+  static_assert(sizeof(S) % 4 == 0, "whole words");
+  unsigned w[sizeof(S) / 4];
+  __builtin_memcpy(w, &s, sizeof(S));
+#pragma unroll
+  for (int i = 0; i < (int)(sizeof(S) / 4); ++i) asm volatile("" : "+v"(w[i]));
+  __builtin_memcpy(&s, w, sizeof(S));
+}
+
 template <int W>
 __device__ __forceinline__ void block_sum256(double (&v)[W], double* sh) {
   block_sum<W, 4>(v, sh);
@@ -253,7 +265,12 @@ __device__ __forceinline__ void reduce_to_finisher(double (&v)[W], double* __res
                          __HIP_MEMORY_SCOPE_AGENT);
   }
   block_sum<W, NW>(acc, sh);
-  if (threadIdx.x == 0) fin(acc, late != 0, snap);
+  // the snapshot's first use: left to itself the compiler moved its uniform
+  // fields to scalar registers right after the loads, waiting for them
+  // before the block sum
+  auto snap_v = snap;
+  in_vgprs(snap_v);
+  if (threadIdx.x == 0) fin(acc, late != 0, snap_v);
 }
 
 __device__ __forceinline__ bool finite(double v) { return __builtin_isfinite(v); }

@@ -144,12 +144,14 @@ struct SolverState {
   double relres;
   double lambda;
   double tol;
+  // (iter, max_iter, fixed, hist_cap and hist are read together by the
+  // CGLS scalar step: one aligned 16-byte and one aligned 8-byte load)
   int iter;          // completed iterations
   int max_iter;
   int fixed;         // run exactly max_iter iterations
+  int hist_cap;      // capacity of hist
   int done;          // 0 running, 1 converged, 2 cap, 3 non-finite
   int init;          // 1 after the initial step
-  int hist_cap;      // capacity of hist
   double* hist;      // device array of relres per iteration (may be null)
   // GMRES
   int j;             // inner steps done in the current cycle
