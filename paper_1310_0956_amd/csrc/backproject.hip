@@ -151,15 +151,21 @@ __device__ __forceinline__ T pixel_term(T J, const T* __restrict__ w, const Meta
   return fma(w0, r0, fma(w1, r1, acc));
 }
 
-// Raw window loads of one chunk.  Thread t stages angle row t / 4 of the
-// chunk's [kChunk][kWin] window, bins t % 4 + 4 i, so its elements share one
-// window start and one row offset, and the lanes of a quad read consecutive
-// bins.  Bins outside [0, nb) and rows past the last angle are read at an
-// offset past the end of the buffer, which loads 0; every load is issued
-// unconditionally, so they are all in flight together.  In the CGLS modes the
-// projected direction is loaded at the same offsets.
+// Raw window loads of one chunk.  Thread t stages angle rows t / 8 and
+// t / 8 + 16 of the chunk's [kChunk][kWin] window, bins t % 8 + 8 i of each,
+// so the lanes of an octet read consecutive bins and a wave's load touches 8
+// rows (the cache lines a load touches bound the staging rate); the LDS
+// stores of a wave then hit distinct banks.  Bins outside [0, nb) and rows
+// past the last angle are read at an offset past the end of the buffer,
+// which loads 0; every load is issued unconditionally, so they are all in
+// flight together.  In the CGLS modes the projected direction is loaded at
+// the same offsets.
 constexpr bool kCglsMode(int mode) { return mode == BWD_CGLS || mode == BWD_CGLS_INIT; }
-static_assert(kThreads == 4 * kChunk && kWin == 4 * kPerThread, "one window row per quad");
+constexpr int kRowLanes = 8;                     // lanes per window row
+constexpr int kRowHalf = kChunk / 2;             // the second row of a thread
+constexpr int kPerRow = kPerThread / 2;          // elements per row and thread
+static_assert(kThreads == kRowLanes * kRowHalf && kWin == kRowLanes * kPerRow,
+              "two window rows per octet");
 
 template <typename T, int MODE>
 struct Stage {
@@ -182,35 +188,53 @@ __device__ __forceinline__ StageSrc stage_src(const BwdK<T>& a) {
   return src;
 }
 
-// rowoff = (t / 4) * nb, the thread's row offset within a chunk, taken once.
+// rowoff = (t / 8) * nb, the offset of the thread's first row within a
+// chunk, taken once.  Elements [0, kPerRow) of sg are the first row's,
+// [kPerRow, 2 kPerRow) the second's.
 template <typename T, int MODE>
 __device__ __forceinline__ void stage_load(Stage<T, MODE>& sg, const StageSrc& src,
                                            const Meta<T>* __restrict__ mt, int k0, int m, int nb,
                                            unsigned rowoff, int t) {
-  const int kk = t >> 2;
-  const int j0 = mt[kk].jw + (t & 3);
-  const bool row = kk < m - k0;
-  // byte offset of bin j0 of angle k0 + kk (valid bins lie below 2^31 bytes)
-  const unsigned off0 = ((unsigned)k0 * (unsigned)nb + rowoff + (unsigned)j0) * (unsigned)sizeof(T);
-  const bool full = row && j0 >= 0 && j0 + 4 * (kPerThread - 1) < nb;
+  const int ka = t / kRowLanes, kb = ka + kRowHalf;
+  const int ja = mt[ka].jw + (t % kRowLanes), jb = mt[kb].jw + (t % kRowLanes);
+  const bool rowa = ka < m - k0, rowb = kb < m - k0;
+  // byte offsets of bins ja of angle k0 + ka and jb of angle k0 + kb (valid
+  // bins lie below 2^31 bytes; rows past the last angle are never read at
+  // these offsets)
+  const unsigned offa = ((unsigned)k0 * (unsigned)nb + rowoff + (unsigned)ja) * (unsigned)sizeof(T);
+  const unsigned offb =
+      ((unsigned)(k0 + kRowHalf) * (unsigned)nb + rowoff + (unsigned)jb) * (unsigned)sizeof(T);
+  constexpr int kSpan = kRowLanes * (kPerRow - 1);
+  const bool full = rowa && rowb && ja >= 0 && ja + kSpan < nb && jb >= 0 && jb + kSpan < nb;
+  constexpr unsigned kStep = kRowLanes * sizeof(T);
   if (__builtin_amdgcn_ballot_w64(!full) == 0) {
     // the whole wave's windows lie on the detector (the common case)
 #pragma unroll
-    for (int i = 0; i < kPerThread; ++i) {
-      const unsigned off = off0 + 4u * i * (unsigned)sizeof(T);
-      sg.r[i] = load_elem(src.sino, off, 0, T(0));
-      if constexpr (kCglsMode(MODE)) sg.q[i] = load_elem(src.q, off, 0, T(0));
+    for (int i = 0; i < kPerRow; ++i) {
+      const unsigned oa = offa + kStep * i, ob = offb + kStep * i;
+      sg.r[i] = load_elem(src.sino, oa, 0, T(0));
+      sg.r[kPerRow + i] = load_elem(src.sino, ob, 0, T(0));
+      if constexpr (kCglsMode(MODE)) {
+        sg.q[i] = load_elem(src.q, oa, 0, T(0));
+        sg.q[kPerRow + i] = load_elem(src.q, ob, 0, T(0));
+      }
     }
   } else {
 #pragma unroll
-    for (int i = 0; i < kPerThread; ++i) {
-      unsigned off = row && (unsigned)(j0 + 4 * i) < (unsigned)nb ? off0 : kOutside;
+    for (int i = 0; i < kPerRow; ++i) {
+      unsigned oa = rowa && (unsigned)(ja + kRowLanes * i) < (unsigned)nb ? offa : kOutside;
+      unsigned ob = rowb && (unsigned)(jb + kRowLanes * i) < (unsigned)nb ? offb : kOutside;
       // keeps the element's constant offset out of the select, so that it
       // becomes the load's immediate offset
-      asm volatile("" : "+v"(off));
-      off += 4u * i * (unsigned)sizeof(T);
-      sg.r[i] = load_elem(src.sino, off, 0, T(0));
-      if constexpr (kCglsMode(MODE)) sg.q[i] = load_elem(src.q, off, 0, T(0));
+      asm volatile("" : "+v"(oa), "+v"(ob));
+      oa += kStep * i;
+      ob += kStep * i;
+      sg.r[i] = load_elem(src.sino, oa, 0, T(0));
+      sg.r[kPerRow + i] = load_elem(src.sino, ob, 0, T(0));
+      if constexpr (kCglsMode(MODE)) {
+        sg.q[i] = load_elem(src.q, oa, 0, T(0));
+        sg.q[kPerRow + i] = load_elem(src.q, ob, 0, T(0));
+      }
     }
   }
 }
@@ -221,12 +245,13 @@ __device__ __forceinline__ void stage_load(Stage<T, MODE>& sg, const StageSrc& s
 template <typename T, int MODE>
 __device__ __forceinline__ void stage_store(const Stage<T, MODE>& sg, T* __restrict__ w,
                                             double alpha, int t) {
-  T* row = w + (t >> 2) * kWin + (t & 3);
+  T* row = w + (t / kRowLanes) * kWin + (t % kRowLanes);
 #pragma unroll
   for (int i = 0; i < kPerThread; ++i) {
     T v = sg.r[i];
     if constexpr (kCglsMode(MODE)) v = (T)((double)sg.r[i] - alpha * (double)sg.q[i]);
-    row[4 * i] = v;
+    const int h = i / kPerRow, e = i % kPerRow;   // row (first or second), element
+    row[h * kRowHalf * kWin + kRowLanes * e] = v;
   }
 }
 
@@ -340,7 +365,7 @@ __device__ __forceinline__ void backward_body(const BwdK<T>& a, const BlockPos p
   const int iy0 = pos.y * kTile + ty, iy1 = iy0 + 8;
   const int n = a.n, nb = a.nb, m = a.m;
   const StageSrc src = stage_src<T, MODE>(a);
-  unsigned rowoff = (unsigned)(t >> 2) * (unsigned)nb;
+  unsigned rowoff = (unsigned)(t / kRowLanes) * (unsigned)nb;
   asm volatile("" : "+v"(rowoff));   // kept as is: not refolded into a product per chunk
   const double hc = 0.5 * (n - 1), hb = uniform(0.5 * (nb - 1));
   const double Xc = uniform(pos.x * kTile + 0.5 * (kTile - 1) - hc);
