@@ -1,0 +1,106 @@
+"""Pins of the Joseph-kernel oracle (Section 2.1 names Joseph's kernel for W).
+
+- Images linear along the interpolation axis: Joseph's sum is the midpoint rule
+  in the followed coordinate of a function that linear interpolation
+  reproduces, so a ray that stays between the outermost pixel centres gets the
+  exact line integral: the chord length 2/|cos a| times the value at the chord
+  midpoint (closed form, no use of the assembly).
+- Where the kernels coincide it equals the exact-length matrix (pinned on its
+  own): at 45 degrees both footprints are the same triangle; at axis angles a
+  ray through pixel centres gives h to each pixel it passes, and a ray on
+  pixel edges h/2 to each neighbour.
+- A planted mistake in the oracle (the interpolation anchored one pixel off)
+  fails the linear pin.
+"""
+import numpy as np
+import pytest
+
+from oracle import joseph
+from oracle.geometry import Geometry, bin_offsets, direction, pixel_centres
+from oracle.projector import angle_block
+
+
+@pytest.mark.parametrize("n,m,nb", [(16, 12, 23), (24, 18, 35), (9, 7, 13)])
+def test_linear_images_give_exact_chord_integrals(n, m, nb):
+    g = Geometry(n, m, nb)
+    h = g.h
+    xc = pixel_centres(n)
+    rng = np.random.default_rng(n)
+    t = bin_offsets(nb, n)
+    checked = 0
+    for k in range(m):
+        c, s = direction(k, m)
+        rows = abs(c) >= abs(s)
+        a, b = (c, s) if rows else (s, c)
+        alpha, beta = rng.normal(), rng.normal()
+        # image linear in the interpolated coordinate (x when rows are followed)
+        vals = alpha + beta * xc
+        img = np.tile(vals, (n, 1)) if rows else np.tile(vals[:, None], (1, n))
+        blk = joseph.joseph_block(g, k)
+        sums = blk @ img.ravel()
+        # rays whose crossing points stay within the outermost centres on every
+        # followed line: |t/a| + |b/a| (1 - h/2) <= 1 - h/2
+        lim = 1.0 - 0.5 * h
+        ok = np.abs(t / a) + abs(b / a) * lim <= lim + 1e-12
+        want = (2.0 / abs(a)) * (alpha + beta * t / a)
+        assert np.allclose(sums[ok], want[ok], rtol=1e-12, atol=1e-12), k
+        checked += int(ok.sum())
+    assert checked > m
+
+
+@pytest.mark.parametrize("n,nb", [(8, 12), (12, 17), (10, 15)])
+def test_equals_exact_lengths_at_45_degrees(n, nb):
+    g = Geometry(n, 4, nb)            # angles 0, 45, 90, 135 degrees
+    for k in (1, 3):
+        J = joseph.joseph_block(g, k).toarray()
+        E = angle_block(g, k).toarray()
+        assert np.allclose(J, E, rtol=0, atol=1e-14 * g.h), k
+
+
+@pytest.mark.parametrize("n,nb", [(8, 8), (8, 9), (7, 7), (7, 8)])
+def test_equals_exact_lengths_on_axis_rays(n, nb):
+    """nb = n: bin centres on pixel centres; nb = n + 1: on pixel edges."""
+    g = Geometry(n, 2, nb)            # 0 and 90 degrees
+    for k in (0, 1):
+        J = joseph.joseph_block(g, k).toarray()
+        E = angle_block(g, k).toarray()
+        assert np.allclose(J, E, rtol=0, atol=1e-14 * g.h), k
+
+
+def test_weights_per_followed_line_sum_to_the_step():
+    n, m, nb = 12, 10, 17
+    g = Geometry(n, m, nb)
+    for k in range(m):
+        c, s = direction(k, m)
+        rows = abs(c) >= abs(s)
+        step = g.h / max(abs(c), abs(s))
+        blk = joseph.joseph_block(g, k).toarray().reshape(nb, n, n)   # [ray][iy][ix]
+        per_line = blk.sum(axis=2) if rows else blk.sum(axis=1)
+        # lines where both interpolation pixels lie inside the image carry the full step
+        full = np.isclose(per_line, step, rtol=1e-12)
+        partial = per_line < step * (1 - 1e-12)
+        assert np.all(full | partial)
+        assert full.sum() > n
+
+
+def test_misplaced_interpolation_fails_the_linear_pin(monkeypatch):
+    """A planted mistake in the oracle (interpolation anchored one pixel off) is caught."""
+    n, m, nb = 16, 12, 23
+    g = Geometry(n, m, nb)
+    k = 2
+    c, s = direction(k, m)
+    orig_floor = np.floor
+
+    def shifted_floor(x):   # anchors the interpolation at floor(P) + 1
+        return orig_floor(x) + 1.0
+
+    monkeypatch.setattr(joseph.np, "floor", shifted_floor)
+    blk = joseph.joseph_block(g, k)
+    monkeypatch.undo()
+    xc = pixel_centres(n)
+    img = np.tile(0.5 + 2.0 * xc, (n, 1))
+    t = bin_offsets(nb, n)
+    want = (2.0 / abs(c)) * (0.5 + 2.0 * t / c)
+    lim = 1.0 - 0.5 * g.h
+    ok = np.abs(t / c) + abs(s / c) * lim <= lim
+    assert not np.allclose((blk @ img.ravel())[ok], want[ok], rtol=1e-6)
