@@ -27,21 +27,23 @@ from __future__ import annotations
 import numpy as np
 import scipy.sparse as sp
 
-from .geometry import Geometry, bin_offsets, direction, pixel_centres
+from .geometry import Geometry, direction
 
 
 def joseph_block(g: Geometry, k: int) -> sp.csr_matrix:
     """Rows k*nb .. k*nb+nb-1 of Joseph's W as an (nb x N) CSR matrix (float64)."""
     n, nb, h = g.n, g.nb, g.h
     c, s = direction(k, g.m)
-    t = bin_offsets(nb, n)
-    centres = pixel_centres(n)
     rows_follow = abs(c) >= abs(s)
     a, b = (c, s) if rows_follow else (s, c)   # p.(c, s) = t solved for the interpolated coordinate
     step = h / abs(a)
-    # crossing point of ray j with centre line r, in pixel index units along the line
-    q = (t[:, None] - centres[None, :] * b) / a
-    P = (q + 1.0) / h - 0.5
+    # crossing point of ray j with centre line r in pixel index units: with
+    # t_j = (j - hb) h and the line at (r - hc) h, the point (t_j - y_r b) / a
+    # is at index hc + ((j - hb) - (r - hc) b) / a (exact for axis rays)
+    hc, hb = 0.5 * (n - 1), 0.5 * (nb - 1)
+    tj = np.arange(nb, dtype=np.float64) - hb
+    yr = np.arange(n, dtype=np.float64) - hc
+    P = hc + (tj[:, None] - yr[None, :] * b) / a
     i0 = np.floor(P)
     f = P - i0
     i0 = i0.astype(np.int64)
