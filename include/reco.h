@@ -8,7 +8,9 @@
  * detector bins of width one pixel centred on the origin (flat index k*nb + j).
  * Ray (k, j) is the line p.(cos theta_k, sin theta_k) = (j - (nb-1)/2) * 2/n and
  * w_ij is the exact length of ray i inside pixel j (a ray lying on a pixel edge
- * gives half of its length to each side).  Krylov methods solve the normal
+ * gives half of its length to each side), or, for geometries created with
+ * RECO_PROJ_JOSEPH, the weight of Joseph's interpolation kernel (Section 2.1).
+ * Either W is applied matrix-free, and its transpose is applied exactly.  Krylov methods solve the normal
  * equations (W^T W + lambda I) x = W^T b (eq. sys_ne, eq. sys_reg).
  *
  * Conventions for every entry point:
@@ -51,6 +53,14 @@ typedef int32_t reco_status;
 #define RECO_PRECOND_NONE 0
 #define RECO_PRECOND_WMG  1
 
+/* Projection kernels (reco_geometry_desc.projector). */
+#define RECO_PROJ_EXACT  0   /* exact ray-pixel intersection lengths */
+#define RECO_PROJ_JOSEPH 1   /* Joseph's kernel (Section 2.1): along the image
+                                axis closest to the ray, linear interpolation
+                                between the two nearest pixel centres of each
+                                row (column) crossed, times the ray length per
+                                row (column), h / max(|cos|, |sin|) */
+
 typedef struct reco_geometry_s* reco_geometry;
 typedef struct reco_server_s* reco_server;
 
@@ -67,7 +77,7 @@ typedef struct {
   int32_t n_bins;
   int32_t wmg_levels;
   int32_t dtype;
-  int32_t reserved;   /* must be 0 */
+  int32_t projector;  /* RECO_PROJ_EXACT (0) or RECO_PROJ_JOSEPH */
 } reco_geometry_desc;
 
 /* Solver options.  tol > 0 is the relative residual target (normal-equation

@@ -22,13 +22,14 @@ RECO_OK, RECO_PENDING, RECO_ENOTCONV = 0, 1, 2
 RECO_EINVAL, RECO_ENOMEM, RECO_EDEVICE, RECO_ENUMERIC, RECO_ENOTFOUND = -1, -2, -3, -4, -5
 F32, F64 = 0, 1
 PRECOND_NONE, PRECOND_WMG = 0, 1
+PROJ_EXACT, PROJ_JOSEPH = 0, 1   # exact intersection lengths / Joseph's kernel
 STATUS_NAMES = {0: "ok", 1: "pending", 2: "not_converged", -1: "einval", -2: "enomem",
                 -3: "edevice", -4: "enumeric", -5: "enotfound"}
 
 
 class GeometryDesc(C.Structure):
     _fields_ = [("n", C.c_int32), ("n_angles", C.c_int32), ("n_bins", C.c_int32),
-                ("wmg_levels", C.c_int32), ("dtype", C.c_int32), ("reserved", C.c_int32)]
+                ("wmg_levels", C.c_int32), ("dtype", C.c_int32), ("projector", C.c_int32)]
 
 
 class SolveOpts(C.Structure):
@@ -146,8 +147,9 @@ def _torch_dtype(dtype):
 class Geometry:
     """A 2D parallel-beam geometry on the GPU (owns tables and the packet diagonal)."""
 
-    def __init__(self, n, n_angles, n_bins, wmg_levels=2, dtype=F32, stream=None):
-        self.desc = GeometryDesc(n, n_angles, n_bins, wmg_levels, dtype, 0)
+    def __init__(self, n, n_angles, n_bins, wmg_levels=2, dtype=F32, stream=None,
+                 projector=PROJ_EXACT):
+        self.desc = GeometryDesc(n, n_angles, n_bins, wmg_levels, dtype, projector)
         h = C.c_void_p()
         _check(_lib.reco_create_geometry(C.byref(self.desc), _stream(stream), C.byref(h)))
         self.handle = h
@@ -308,7 +310,7 @@ class Server:
         self.handle = h
 
     def submit(self, n, n_angles, n_bins, wmg_levels, b, x, tol=1e-3, max_iter=1000,
-               precond=PRECOND_WMG, lam=0.0, fixed_iters=0):
+               precond=PRECOND_WMG, lam=0.0, fixed_iters=0, projector=PROJ_EXACT):
         """Queue a request; b and x are float32 device tensors that must stay alive
         (and b unchanged) until poll() returns a result.  The current stream is
         synchronised first so that b is complete when the server reads it."""
@@ -319,7 +321,7 @@ class Server:
                 raise ValueError(f"{name} must be a contiguous float32 GPU tensor of {size} "
                                  "elements")
         torch.cuda.current_stream().synchronize()
-        desc = GeometryDesc(n, n_angles, n_bins, wmg_levels, F32, 0)
+        desc = GeometryDesc(n, n_angles, n_bins, wmg_levels, F32, projector)
         opts = SolveOpts(float(tol), int(max_iter), 30, float(lam), int(precond), 0, None, 0,
                          int(fixed_iters))
         t = C.c_uint64()

@@ -11,9 +11,10 @@
 // LDS ring, filled from angle records fetched two chunks ahead, so no chunk
 // waits on them.  Every pixel then reads its two candidate
 // bins floor(J) and floor(J)+1, J being the bin coordinate of the pixel
-// centre, and weights them with the same exact intersection length w(t) the
-// forward projector uses (trapezoid in the ray offset t), so the result is the
-// transpose of the forward matrix up to rounding.  Pixel coordinates are taken
+// centre, and weights them with the same weight w(t) the forward projector
+// uses (the exact intersection length, a trapezoid in the ray offset t, or
+// Joseph's triangle), so the result is the transpose of the forward matrix up
+// to rounding.  Pixel coordinates are taken
 // relative to the tile centre, whose bin coordinate is computed in float64.
 #include "device_common.h"
 #include "timing.h"

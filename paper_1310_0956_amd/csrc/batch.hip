@@ -449,7 +449,7 @@ struct Request {
   bool fresh_ws = false;  // admission added a workspace (none was pooled)
 };
 
-using DescKey = std::tuple<int, int, int, int, int>;
+using DescKey = std::tuple<int, int, int, int, int, int>;
 
 struct GeoEntry {
   reco_geometry_desc desc{};
@@ -464,7 +464,7 @@ struct GeoEntry {
 };
 
 DescKey key_of(const reco_geometry_desc& d) {
-  return DescKey{d.n, d.n_angles, d.n_bins, d.wmg_levels, d.dtype};
+  return DescKey{d.n, d.n_angles, d.n_bins, d.wmg_levels, d.dtype, d.projector};
 }
 
 }  // namespace
@@ -915,7 +915,8 @@ reco_status reco_submit(reco_server h, const reco_geometry_desc* desc, const voi
   reco::Server* s = reinterpret_cast<reco::Server*>(h);
   try {
     if (desc->dtype != RECO_F32) reco::fail(RECO_EINVAL, "the server solves RECO_F32 problems");
-    if (desc->reserved != 0) reco::fail(RECO_EINVAL, "reserved must be 0");
+    if (desc->projector != RECO_PROJ_EXACT && desc->projector != RECO_PROJ_JOSEPH)
+      reco::fail(RECO_EINVAL, "projector must be RECO_PROJ_EXACT or RECO_PROJ_JOSEPH");
     if (desc->n < 2 || desc->n > 65536 || desc->n_angles < 1 || desc->n_bins < 1 ||
         desc->wmg_levels < 1 || desc->wmg_levels > 6 ||
         desc->n % (1 << (desc->wmg_levels - 1)) != 0)

@@ -23,8 +23,16 @@ void direction(int k, int m, double& c, double& s) {
 }
 }  // namespace
 
+// Both kernels weigh, per row (column) crossed, the two pixels nearest to the
+// ray with w0 = clamp((1/2 - f) B + C, 0, 1/u), w1 = 1/u - w0 (units of h; f the
+// fractional crossing position, u >= v the larger and smaller of |cos|, |sin|).
+// Exact lengths: B = 1/v, a trapezoid in the ray offset with plateau (u - v)/2
+// and support (u + v)/2.  Joseph's kernel is the same form with v replaced by u
+// in the weights (B = 1/u: w0 = (1 - f)/u, the linear interpolation), a
+// triangle of support u; the ray directions are unchanged.
 void build_angle_tables(Geometry& g) {
   const int n = g.n, m = g.m, nb = g.nb;
+  const bool joseph = g.desc.projector == RECO_PROJ_JOSEPH;
   g.h_fwd.resize(m);
   g.h_bwd.resize(m);
   const double hc = 0.5 * (n - 1), hb = 0.5 * (nb - 1);
@@ -36,7 +44,7 @@ void build_angle_tables(Geometry& g) {
     f.major = (std::fabs(c) >= std::fabs(s)) ? 0 : 1;
     const double a = f.major ? s : c;   // |a| = u >= |b| = v
     const double b = f.major ? c : s;
-    const double u = std::fabs(a), v = std::fabs(b);
+    const double u = std::fabs(a), v = joseph ? u : std::fabs(b);
     f.A0 = hc + (hc * b - hb) / a;
     f.inv = 1.0 / a;
     f.slope = -b / a;
@@ -51,7 +59,7 @@ void build_angle_tables(Geometry& g) {
     // ---- backward: trapezoid in bin units
     BwdAngle w{};
     const double uu = std::max(std::fabs(c), std::fabs(s));
-    const double vv = std::min(std::fabs(c), std::fabs(s));
+    const double vv = joseph ? uu : std::min(std::fabs(c), std::fabs(s));
     w.c = c;
     w.s = s;
     w.B = vv > 0 ? 1.0 / (uu * vv) : kAxisSlope;
@@ -98,7 +106,8 @@ Geometry* create_geometry(const reco_geometry_desc& d, hipStream_t st) {
   if (d.n_bins < 1) fail(RECO_EINVAL, "n_bins must be >= 1");
   if (d.wmg_levels < 1 || d.wmg_levels > 6) fail(RECO_EINVAL, "wmg_levels must be in [1, 6]");
   if (d.dtype != RECO_F32 && d.dtype != RECO_F64) fail(RECO_EINVAL, "dtype must be RECO_F32 or RECO_F64");
-  if (d.reserved != 0) fail(RECO_EINVAL, "reserved must be 0");
+  if (d.projector != RECO_PROJ_EXACT && d.projector != RECO_PROJ_JOSEPH)
+    fail(RECO_EINVAL, "projector must be RECO_PROJ_EXACT or RECO_PROJ_JOSEPH");
   const int L = d.wmg_levels - 1;
   if (d.n % (1 << L) != 0) fail(RECO_EINVAL, "n must be divisible by 2^(wmg_levels-1)");
   // The projectors address the padded image copies and the sinogram with

@@ -3,12 +3,13 @@
 // Each ray is walked along its major axis: at every row (or column, for angles
 // closer to the x axis, via a transposed image copy) the ray overlaps exactly
 // two candidate pixels, floor(P) and floor(P)+1, where P is the crossing
-// position in pixel units.  With f = P - floor(P) the exact intersection
-// lengths are
+// position in pixel units.  With f = P - floor(P) the weights are
 //   w0 = h clamp((1/2 - f) B + C, 0, 1/u),  w1 = h/u - w0,
-// u = |major direction cosine|, B = 1/v, C = 1/(2u), v = |minor cosine| (the
-// trapezoid of the chord length against the ray offset; the two weights of a
-// row always add up to the row's chord h/u).  Candidate columns are clamped to
+// u = |major direction cosine|, C = 1/(2u), from per-angle tables: for the
+// exact intersection lengths B = 1/v, v = |minor cosine| (the trapezoid of
+// the chord length against the ray offset), for Joseph's kernel B = 1/u
+// (w0 = h (1 - f)/u, the linear interpolation); the two weights of a row
+// always add up to the row's chord h/u.  Candidate columns are clamped to
 // [-2, n]; the padded image copies carry kPad >= 2 zero columns on each side,
 // so a ray outside the image reads zeros.
 //
