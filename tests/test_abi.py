@@ -63,3 +63,37 @@ def test_invalid_arguments_rejected_without_gpu_work():
     assert lib.reco_submit(None, None, None, None, None, None) == reco.RECO_EINVAL
     assert lib.reco_poll(None, 1, None, None) == reco.RECO_EINVAL
     assert lib.reco_server_destroy(None) == reco.RECO_OK
+
+
+_CTYPE = {"int32_t": ctypes.c_int32, "reco_status": ctypes.c_int32, "double": ctypes.c_double,
+          "double*": ctypes.POINTER(ctypes.c_double)}
+
+
+def _header_struct(name):
+    """(field, C type) pairs of `typedef struct { ... } name;` in the header."""
+    txt = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    body = re.search(r"typedef struct\s*\{([^}]*)\}\s*" + name + r"\s*;", txt).group(1)
+    fields = []
+    for decl in body.split(";"):
+        decl = decl.strip()
+        if not decl:
+            continue
+        m = re.match(r"(\w+)\s*(\*?)\s*(\w+)$", decl)
+        fields.append((m.group(3), m.group(1) + m.group(2)))
+    return fields
+
+
+def test_binding_structs_match_header():
+    """The ctypes structures have the header's fields, in order, with the same types
+    (so sizes and offsets agree)."""
+    import paper_1310_0956_amd as reco
+    for cname, py in (("reco_geometry_desc", reco.GeometryDesc), ("reco_solve_opts", reco.SolveOpts),
+                      ("reco_solve_info", reco.SolveInfo)):
+        hdr = _header_struct(cname)
+        assert len(hdr) == len(py._fields_), cname
+        for (hname, htype), (_, ptype) in zip(hdr, py._fields_):
+            want = _CTYPE[htype]
+            assert ctypes.sizeof(ptype) == ctypes.sizeof(want), (cname, hname)
+            assert type(ptype) is type(want) or ptype is want, (cname, hname)
+    assert [f for f, _ in _header_struct("reco_geometry_desc")][-1] == "projector"
+    assert reco.PROJ_EXACT == 0 and reco.PROJ_JOSEPH == 1
