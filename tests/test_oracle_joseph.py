@@ -104,3 +104,82 @@ def test_misplaced_interpolation_fails_the_linear_pin(monkeypatch):
     lim = 1.0 - 0.5 * g.h
     ok = np.abs(t / c) + abs(s / c) * lim <= lim
     assert not np.allclose((blk @ img.ravel())[ok], want[ok], rtol=1e-6)
+
+
+def _kernel_form(g, joseph_coefficients):
+    """W from the projectors' weight form, pixel driven: for pixel centre bin
+    coordinate J (f = J - floor J) the bins floor J and floor J + 1 weigh
+    clamp(C0 - f B) and clamp(C1 + f B) in [0, 1/u] (units of h), with
+    B = 1/(u v), C0 = 1/(2u) + u B / 2, C1 = 1/(2u) + (u/2 - 1) B; exact
+    lengths take v = min(|cos|, |sin|), Joseph's kernel v = u (reading D30)."""
+    n, m, nb = g.n, g.m, g.nb
+    hc, hb = 0.5 * (n - 1), 0.5 * (nb - 1)
+    W = np.zeros((g.M, g.N))
+    iy, ix = np.divmod(np.arange(g.N), n)
+    for k in range(m):
+        c, s = direction(k, m)
+        u = max(abs(c), abs(s))
+        v = u if joseph_coefficients else min(abs(c), abs(s))
+        if v == 0.0:
+            continue
+        B = 1.0 / (u * v)
+        C0 = 0.5 / u + 0.5 * u * B
+        C1 = 0.5 / u + (0.5 * u - 1.0) * B
+        Jc = (ix - hc) * c + (iy - hc) * s + hb
+        j0 = np.floor(Jc)
+        f = Jc - j0
+        for j, w in ((j0, np.clip(C0 - f * B, 0.0, 1.0 / u)), (j0 + 1, np.clip(C1 + f * B, 0.0, 1.0 / u))):
+            ok = (j >= 0) & (j < nb) & (w > 0)
+            W[k * nb + j[ok].astype(int), np.arange(g.N)[ok]] += w[ok] * g.h
+    return W
+
+
+@pytest.mark.parametrize("n,m,nb", [(24, 18, 35), (16, 7, 23), (9, 10, 13)])
+def test_kernel_weight_form_with_v_equal_u_is_joseph(n, m, nb):
+    """Reading D30: the weight coefficients of the exact-length kernels with v replaced by u
+    give Joseph's kernel (angles off the axes; the kernels treat v = 0 with a finite slope)."""
+    g = Geometry(n, m, nb)
+    J = joseph.joseph_matrix(g).toarray()
+    K = _kernel_form(g, True)
+    rows = np.concatenate([np.arange(k * nb, (k + 1) * nb) for k in range(m)
+                           if min(abs(c) for c in direction(k, m)) > 0])
+    assert np.abs(K[rows] - J[rows]).max() <= 1e-13 * g.h
+    # and with v = min(|cos|, |sin|) the same form is the exact-length matrix
+    E = angle_block_stack(g)
+    Ke = _kernel_form(g, False)
+    assert np.abs(Ke[rows] - E[rows]).max() <= 1e-12 * g.h
+
+
+def angle_block_stack(g):
+    return np.vstack([angle_block(g, k).toarray() for k in range(g.m)])
+
+
+@pytest.mark.parametrize("n,m,nb", [(24, 18, 35), (16, 7, 23)])
+def test_forward_weight_form_with_v_equal_u_is_joseph(n, m, nb):
+    """The forward projector's per-row form w0 = clamp((1/2 - f) B + C, 0, 1/u),
+    w1 = 1/u - w0 with B = 1/u, C = 1/(2u) (reading D30) is Joseph's interpolation:
+    ray sums of random images agree with the oracle."""
+    g = Geometry(n, m, nb)
+    rng = np.random.default_rng(7)
+    x = rng.random(g.N)
+    J = joseph.joseph_matrix(g)
+    hc, hb = 0.5 * (n - 1), 0.5 * (nb - 1)
+    img = x.reshape(n, n)
+    for k in range(m):
+        c, s = direction(k, m)
+        rows = abs(c) >= abs(s)
+        a, b = (c, s) if rows else (s, c)
+        u = abs(a)
+        B, C = 1.0 / u, 0.5 / u
+        got = np.zeros(nb)
+        for j in range(nb):
+            for r in range(n):
+                P = hc + ((j - hb) - (r - hc) * b) / a
+                i0 = int(np.floor(P))
+                f = P - i0
+                w0 = min(max((0.5 - f) * B + C, 0.0), 1.0 / u)
+                for i, w in ((i0, w0), (i0 + 1, 1.0 / u - w0)):
+                    if 0 <= i < n:
+                        got[j] += w * g.h * (img[r, i] if rows else img[i, r])
+        want = (J @ x)[k * nb:(k + 1) * nb]
+        assert np.allclose(got, want, rtol=1e-12, atol=1e-14), k
