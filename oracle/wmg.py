@@ -21,7 +21,16 @@ Variants:
 Parity status: packet_diagonal pinned by brute force against dense
 diag(H_L W^T W H_L^T) on small grids; the additive variants pinned by the
 block-diagonal exactness property (K = H_L^T B H_L with B block diagonal is
-inverted exactly).
+inverted exactly).  WaveletCycle: on real projection matrices the one-level
+error propagation I - M^-1 A is pinned against its closed form for every mode
+(multiplicative: the product of the four A-orthogonal projections of eq. wmg;
+hybrid: (I - sum_{LH,HL,HH} P_id A)(I - P_LL A); additive: I - sum_id P_id A,
+with P_id = R_id^T (R_id A R_id^T)^-1 R_id); the two-level hybrid cycle against
+the same formula with each subband's projection replaced by its own one-level
+cycle; the additive cycle recursed to depth L against the packet-basis
+block-Jacobi operator built from H_L (apply_additive_exact).  Planted mistakes
+(the hybrid residual update dropped, the wavelet corrections taken before the
+LL one) fail these pins.
 """
 from __future__ import annotations
 

@@ -113,3 +113,134 @@ def test_preconditioners_reduce_condition_number():
     # the additive-diagonal operator is symmetric positive definite
     assert np.allclose(Mdiag, Mdiag.T, atol=1e-12)
     assert np.linalg.eigvalsh(0.5 * (Mdiag + Mdiag.T)).min() > 0
+
+
+# --- hybrid and additive cycles (Section 3.1.2, eq. wmg and the hybrid variant) ---
+
+def _projection(A, R):
+    """P = R^T (R A R^T)^-1 R: the A-orthogonal projection onto range(R^T), times A^-1."""
+    return R.T @ np.linalg.solve(R @ A @ R.T, R)
+
+
+def _real_system(n, m, nb, lam):
+    Wd = system_matrix(Geometry(n, m, nb)).toarray()
+    return Wd.T @ Wd + lam * np.eye(n * n)
+
+
+def _cycle_matrix(cyc, N):
+    return np.column_stack([cyc(e) for e in np.eye(N)])
+
+
+class _HybridWithoutUpdate(wmg.WaveletCycle):
+    """Planted mistake: the hybrid cycle with its residual update r2 = r - A e dropped."""
+
+    def _cycle(self, node, r):
+        if node[0] == "leaf":
+            return sla.cho_solve(node[1], r)
+        _, A, kids = node
+        R, sub = kids["LL"]
+        e = R.T @ self._cycle(sub, R @ r)
+        for name in self.ORDER[1:]:
+            R, sub = kids[name]
+            e = e + R.T @ self._cycle(sub, R @ r)   # r, not r - A e
+        return e
+
+
+class _HybridHighFirst(wmg.WaveletCycle):
+    """Planted mistake: the three wavelet corrections before the LL one."""
+
+    def _cycle(self, node, r):
+        if node[0] == "leaf":
+            return sla.cho_solve(node[1], r)
+        _, A, kids = node
+        e = np.zeros_like(r)
+        for name in self.ORDER[1:]:
+            R, sub = kids[name]
+            e = e + R.T @ self._cycle(sub, R @ r)
+        r2 = r - A @ e
+        R, sub = kids["LL"]
+        return e + R.T @ self._cycle(sub, R @ r2)
+
+
+def _hybrid_error_propagation(A, n):
+    """One level: E = (I - sum_{LH,HL,HH} P_id A)(I - P_LL A)."""
+    ops = haar.step_operators_2d(n)
+    I = np.eye(n * n)
+    P = {k: _projection(A, ops[k].toarray()) for k in ("LL", "LH", "HL", "HH")}
+    high = P["LH"] + P["HL"] + P["HH"]
+    return (I - high @ A) @ (I - P["LL"] @ A)
+
+
+def _additive_error_propagation(A, n):
+    ops = haar.step_operators_2d(n)
+    S = sum(_projection(A, ops[k].toarray()) for k in ("LL", "LH", "HL", "HH"))
+    return np.eye(n * n) - S @ A
+
+
+@pytest.mark.parametrize("n,m,nb,lam", [(8, 16, 12, 0.1), (8, 7, 11, 0.0), (16, 24, 23, 0.02)])
+def test_hybrid_error_propagation(n, m, nb, lam):
+    """Hybrid WTG on a real geometry: I - M^-1 A equals the product of the LL
+    projection and the summed wavelet projections, LL first."""
+    A = _real_system(n, m, nb, lam)
+    want = _hybrid_error_propagation(A, n)
+    scale = np.abs(want).max()
+    got = np.eye(n * n) - _cycle_matrix(wmg.WaveletCycle(A, n, 1, "hybrid"), n * n) @ A
+    assert np.abs(got - want).max() <= 1e-9 * scale
+    # planted mistakes in the oracle: both must fail this pin
+    for bad in (_HybridWithoutUpdate, _HybridHighFirst):
+        wrong = np.eye(n * n) - _cycle_matrix(bad(A, n, 1, "hybrid"), n * n) @ A
+        assert np.abs(wrong - want).max() > 1e-3 * scale, bad.__name__
+
+
+@pytest.mark.parametrize("n,m,nb,lam", [(8, 16, 12, 0.1), (16, 24, 23, 0.0)])
+def test_additive_error_propagation(n, m, nb, lam):
+    """Additive WTG: I - M^-1 A = I - sum over the four subbands of P_id A."""
+    A = _real_system(n, m, nb, lam)
+    want = _additive_error_propagation(A, n)
+    scale = np.abs(want).max()
+    got = np.eye(n * n) - _cycle_matrix(wmg.WaveletCycle(A, n, 1, "additive"), n * n) @ A
+    assert np.abs(got - want).max() <= 1e-9 * scale
+    # the hybrid cycle (one extra residual update) is a different operator
+    hyb = np.eye(n * n) - _cycle_matrix(wmg.WaveletCycle(A, n, 1, "hybrid"), n * n) @ A
+    assert np.abs(hyb - want).max() > 1e-3 * scale
+
+
+@pytest.mark.parametrize("n,L", [(8, 2), (16, 2), (16, 3)])
+def test_recursive_additive_cycle_is_packet_block_jacobi(n, L):
+    """The additive cycle recursed to depth L with exact coarsest solves equals the
+    block-Jacobi preconditioner of the packet basis, sum_p V_p (V_p^T K V_p)^-1 V_p^T,
+    built independently from the packet matrix H_L and the sparse W."""
+    W = system_matrix(Geometry(n, 3 * n // 2, n + 3))
+    K = (W.T @ W).toarray() + 0.05 * np.eye(n * n)
+    cyc = wmg.WaveletCycle(K, n, L, "additive")
+    F = sla.cholesky(K, lower=False)
+    blocks = wmg.galerkin_blocks(F, n, L)
+    rng = np.random.default_rng(12)
+    for _ in range(3):
+        r = rng.standard_normal(n * n)
+        a = cyc(r)
+        b = wmg.apply_additive_exact(r, blocks, n, L)
+        assert np.linalg.norm(a - b) <= 1e-10 * np.linalg.norm(b)
+
+
+def test_recursive_hybrid_two_levels():
+    """Two levels: the hybrid cycle's error propagation factors as the top-level
+    product with each subband's exact projection replaced by that subband's own
+    (one level down) hybrid cycle, I - (Q_H + Q_LL - Q_H A Q_LL) A, where
+    Q_id = R_id^T B_id R_id and I - B_id A_id is the one-level formula on A_id."""
+    n, lam = 8, 0.05
+    A = _real_system(n, 12, 12, lam)
+    ops = haar.step_operators_2d(n)
+    Q = {}
+    for k in ("LL", "LH", "HL", "HH"):
+        R = ops[k].toarray()
+        Ak = R @ A @ R.T
+        Ek = _hybrid_error_propagation(Ak, n // 2)
+        Bk = np.linalg.solve(Ak.T, (np.eye(Ak.shape[0]) - Ek).T).T   # (I - E_k) A_k^-1
+        Q[k] = R.T @ Bk @ R
+    QH = Q["LH"] + Q["HL"] + Q["HH"]
+    Minv = Q["LL"] + QH - QH @ A @ Q["LL"]
+    got = _cycle_matrix(wmg.WaveletCycle(A, n, 2, "hybrid"), n * n)
+    assert np.abs(got - Minv).max() <= 1e-9 * np.abs(Minv).max()
+    bad = _cycle_matrix(_HybridWithoutUpdate(A, n, 2, "hybrid"), n * n)
+    assert np.abs(bad - Minv).max() > 1e-3 * np.abs(Minv).max()
