@@ -18,6 +18,7 @@
 #include <algorithm>
 #include <condition_variable>
 #include <deque>
+#include <exception>
 #include <map>
 #include <thread>
 #include <tuple>
@@ -372,11 +373,22 @@ void fill_info(const Slot& s, reco_solve_info* info) {
   info->elapsed_ms = s.t_done - s.t_admit;
 }
 
+// A finished problem's workspace is not pooled again when its solve ended
+// abnormally (see ReusePool).
+void mark_if_unusable(Slot& s) {
+  if (!workspace_reusable(s.fin.done, s.failed, false)) s.w->tainted = true;
+}
+
 // Workspaces checked out for a batch, returned on every exit path.
 struct Leases {
   std::vector<std::pair<Geometry*, Workspace*>> held;
+  int unwinding0 = std::uncaught_exceptions();
   ~Leases() {
-    for (auto& p : held) return_workspace(*p.first, p.second);
+    const bool unwinding = std::uncaught_exceptions() > unwinding0;
+    for (auto& p : held) {
+      if (unwinding) p.second->tainted = true;
+      return_workspace(*p.first, p.second);
+    }
   }
 };
 
@@ -416,6 +428,7 @@ reco_status solve_batch(int32_t count, const reco_geometry* geoms, const void* c
   while (!eng.empty()) eng.tick();
   reco_status worst = RECO_OK;
   for (int i = 0; i < count; ++i) {
+    mark_if_unusable(slots[i]);
     fill_info(slots[i], info ? &info[i] : nullptr);
     const reco_status rc = slots[i].failed ? RECO_EDEVICE : status_of(slots[i].fin.done);
     if (rc != RECO_OK && (worst == RECO_OK || rc < 0)) worst = rc;
@@ -806,7 +819,11 @@ void Server::run(int tier) {
           for (Slot* s : done) {
             Request* r = (Request*)s->owner;
             GeoEntry& e = geos[key_of(r->desc)];
-            return_workspace(*e.g, s->w);
+            mark_if_unusable(*s);
+            if (!return_workspace(*e.g, s->w)) {   // dropped: no longer held
+              --e.workspaces;
+              used -= e.ws_bytes;
+            }
             --e.running;
             --running;
             fill_info(*s, &r->info);

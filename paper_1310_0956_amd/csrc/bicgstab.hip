@@ -345,6 +345,7 @@ reco_status solve_bicgstab(Geometry& g, const void* b, void* x, const reco_solve
     rc = g.f64 ? bicgstab_impl<double>(g, b, x, o, info, st, *w)
                : bicgstab_impl<float>(g, b, x, o, info, st, *w);
   } catch (...) {
+    w->tainted = true;
     return_workspace(g, w);
     throw;
   }

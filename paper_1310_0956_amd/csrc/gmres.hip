@@ -413,6 +413,7 @@ reco_status solve_gmres(Geometry& g, const void* b, void* x, const reco_solve_op
     rc = g.f64 ? gmres_impl<double>(g, b, x, o, info, st, *w)
                : gmres_impl<float>(g, b, x, o, info, st, *w);
   } catch (...) {
+    w->tainted = true;
     return_workspace(g, w);
     throw;
   }

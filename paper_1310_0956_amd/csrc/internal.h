@@ -12,6 +12,7 @@
 #include <vector>
 
 #include "../../include/reco.h"
+#include "pool.h"
 
 namespace reco {
 
@@ -118,8 +119,7 @@ struct Geometry {
   void* d_sirtC = nullptr;
 
   // pool of solver workspaces
-  std::mutex ws_mu;
-  std::vector<Workspace*> ws_free;
+  ReusePool<Workspace> ws_pool;
 
   size_t N() const { return (size_t)n * n; }
   size_t M() const { return (size_t)m * nb; }

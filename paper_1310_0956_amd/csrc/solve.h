@@ -27,11 +27,14 @@ struct Workspace {
   int v_cap = 0;                              // vectors allocated in V
   double* gm = nullptr;                       // GMRES / BiCGStab small dense data
   size_t gm_cap = 0;                          // doubles allocated in gm
+  bool tainted = false;                       // last solve ended abnormally: never pooled
   ~Workspace();
 };
 
 Workspace* checkout_workspace(Geometry& g, hipStream_t st);
-void return_workspace(Geometry& g, Workspace* w);
+// Pool w again, or free it (after waiting for the device) when w->tainted or
+// its last polled state says a reduction gave up.  True when pooled.
+bool return_workspace(Geometry& g, Workspace* w);
 void release_workspaces(Geometry& g);
 void ensure_aux(Geometry& g, Workspace& w);     // xP, xTP, tmp, fvec
 void ensure_history(Workspace& w, int cap);

@@ -7,6 +7,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <exception>
 
 #include "device_common.h"
 #include "solve.h"
@@ -31,14 +32,7 @@ static void alloc(void** p, size_t bytes) {
 }
 
 Workspace* checkout_workspace(Geometry& g, hipStream_t st) {
-  {
-    std::lock_guard<std::mutex> lk(g.ws_mu);
-    if (!g.ws_free.empty()) {
-      Workspace* w = g.ws_free.back();
-      g.ws_free.pop_back();
-      return w;
-    }
-  }
+  if (Workspace* w = g.ws_pool.take()) return w;
   std::unique_ptr<Workspace> w(new Workspace());
   const size_t es = g.esize();
   alloc(&w->r, es * g.M());
@@ -54,6 +48,7 @@ Workspace* checkout_workspace(Geometry& g, hipStream_t st) {
   alloc((void**)&w->st, sizeof(SolverState));
   if (hipHostMalloc((void**)&w->h_st, sizeof(SolverState), hipHostMallocDefault) != hipSuccess)
     fail(RECO_ENOMEM, "pinned host allocation failed");
+  std::memset(w->h_st, 0, sizeof(SolverState));
   HIP_CHECK(hipMemsetAsync(w->counter, 0, sizeof(unsigned) * 4, st));
   double empty;
   std::memcpy(&empty, &kSlotEmpty, sizeof(empty));
@@ -96,15 +91,19 @@ size_t geometry_bytes(const reco_geometry_desc& d) {
          blocks * ((bands + 1) * 8 + 4 + sizeof(FwdBlk)) + N * (8 + es) + 4096;
 }
 
-void return_workspace(Geometry& g, Workspace* w) {
-  std::lock_guard<std::mutex> lk(g.ws_mu);
-  g.ws_free.push_back(w);
+bool return_workspace(Geometry& g, Workspace* w) {
+  if (!w) return false;
+  const int done = w->h_st ? w->h_st->done : 0;
+  const bool reusable = workspace_reusable(done, w->tainted, false);
+  return g.ws_pool.give_back(w, reusable, [](Workspace* p) {
+    // late partial stores or queued kernels may still target its buffers
+    (void)hipDeviceSynchronize();
+    delete p;
+  });
 }
 
 void release_workspaces(Geometry& g) {
-  std::lock_guard<std::mutex> lk(g.ws_mu);
-  for (Workspace* w : g.ws_free) delete w;
-  g.ws_free.clear();
+  g.ws_pool.drain([](Workspace* p) { delete p; });
 }
 
 void ensure_history(Workspace& w, int cap) {
@@ -130,8 +129,13 @@ RedScratch red_of(Workspace& w, int slot) {
 struct Lease {
   Geometry& g;
   Workspace* w;
-  Lease(Geometry& gg, hipStream_t st) : g(gg), w(checkout_workspace(gg, st)) {}
-  ~Lease() { return_workspace(g, w); }
+  int unwinding0;
+  Lease(Geometry& gg, hipStream_t st)
+      : g(gg), w(checkout_workspace(gg, st)), unwinding0(std::uncaught_exceptions()) {}
+  ~Lease() {
+    if (std::uncaught_exceptions() > unwinding0) w->tainted = true;
+    return_workspace(g, w);
+  }
 };
 
 void validate_opts(const reco_solve_opts& o, bool gmres) {

@@ -51,6 +51,18 @@ def phantom_and_data(n, m, nb, n_ellipses, seed, noise=0.0, dtype64=False):
     return x, b
 
 
+def check_diag_elementwise(d, d_ref, tol):
+    """Every packet coefficient within tol of its own oracle value."""
+    d = np.asarray(d, dtype=np.float64).ravel()
+    d_ref = np.asarray(d_ref, dtype=np.float64).ravel()
+    zero = d_ref == 0.0
+    assert np.all(d[zero] == 0.0), "packet diagonal: nonzero where the oracle has an exact zero"
+    e = np.abs(d[~zero] - d_ref[~zero]) / d_ref[~zero]
+    print("packet diagonal: max elementwise rel err", float(e.max(initial=0.0)),
+          "zeros", int(zero.sum()), flush=True)
+    assert e.max(initial=0.0) <= tol
+
+
 def print_case(*args):
     print("CASE", *args, flush=True)
 
