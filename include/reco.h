@@ -171,6 +171,28 @@ reco_status reco_solve_cgls(reco_geometry g, const void* b, void* x,
                             const reco_solve_opts* opts, reco_solve_info* info,
                             void* stream);
 
+/* For callers that cannot allocate (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): reco_solve_cgls with every
+ * solver buffer (residuals, direction, padded image copies, reduction
+ * partials, device state, residual history) carved from one fixed device
+ * array of RECO_NOALLOC_SCRATCH_BYTES that the library holds on each device
+ * it runs on until the process ends, and the host copy of the solver state
+ * on the caller's stack.  The call makes no device or host allocation; the
+ * caller passes b and x as for reco_solve_cgls and gets the same result.
+ * Limits: the geometry's CGLS buffers plus 8 bytes per history entry
+ * (max_iter, or fixed_iters) must fit in the array (about 4 * (2 M + 4 N)
+ * bytes for RECO_F32, twice that for RECO_F64: a 1024 x 1024 image with
+ * 1448 angles of 1449 bins fits), else RECO_EINVAL with the sizes in the
+ * message and nothing enqueued; per-kernel timing (reco_timing_enable) must
+ * be off, else RECO_EINVAL.  All calls on one device share the array, so
+ * calls that overlap on one device (other threads, other streams) race; the
+ * array keeps the last call's contents, and each call re-initialises what
+ * the kernels rely on before its first launch.  Synchronous. */
+#define RECO_NOALLOC_SCRATCH_BYTES (64u * 1024u * 1024u)
+reco_status reco_solve_cgls_noalloc(reco_geometry g, const void* b, void* x,
+                                    const reco_solve_opts* opts, reco_solve_info* info,
+                                    void* stream);
+
 /* GMRES(restart) on the right-preconditioned system (W^T W + lambda I) M^-1 u
  * = W^T b, x = M^-1 u (eq. sys_prec, second form).  Otherwise as
  * reco_solve_cgls. */

@@ -21,6 +21,7 @@ _lib = C.CDLL(LIB_PATH)
 RECO_OK, RECO_PENDING, RECO_ENOTCONV = 0, 1, 2
 RECO_EINVAL, RECO_ENOMEM, RECO_EDEVICE, RECO_ENUMERIC, RECO_ENOTFOUND = -1, -2, -3, -4, -5
 F32, F64 = 0, 1
+NOALLOC_SCRATCH_BYTES = 64 * 1024 * 1024   # RECO_NOALLOC_SCRATCH_BYTES
 PRECOND_NONE, PRECOND_WMG = 0, 1
 PROJ_EXACT, PROJ_JOSEPH = 0, 1   # exact intersection lengths / Joseph's kernel
 STATUS_NAMES = {0: "ok", 1: "pending", 2: "not_converged", -1: "einval", -2: "enomem",
@@ -63,6 +64,8 @@ _sig = {
     "reco_backproject": (_S, [_P, _P, _P, _P]),
     "reco_wmg_apply": (_S, [_P, _P, _P, C.c_double, _P]),
     "reco_solve_cgls": (_S, [_P, _P, _P, C.POINTER(SolveOpts), C.POINTER(SolveInfo), _P]),
+    "reco_solve_cgls_noalloc": (_S, [_P, _P, _P, C.POINTER(SolveOpts), C.POINTER(SolveInfo),
+                                     _P]),
     "reco_solve_gmres": (_S, [_P, _P, _P, C.POINTER(SolveOpts), C.POINTER(SolveInfo), _P]),
     "reco_solve_bicgstab": (_S, [_P, _P, _P, C.POINTER(SolveOpts), C.POINTER(SolveInfo), _P]),
     "reco_solve_sirt": (_S, [_P, _P, _P, C.POINTER(SolveOpts), C.POINTER(SolveInfo), _P]),
@@ -258,6 +261,13 @@ class Geometry:
     def solve_cgls(self, b, x=None, tol=1e-3, max_iter=1000, lam=0.0, precond=PRECOND_WMG,
                    fixed_iters=0, history=False, check_every=0, stream=None):
         return self._solve(_lib.reco_solve_cgls, b, x, tol, max_iter, lam, precond, 30,
+                           fixed_iters, history, check_every, stream)
+
+    def solve_cgls_noalloc(self, b, x=None, tol=1e-3, max_iter=1000, lam=0.0,
+                           precond=PRECOND_WMG, fixed_iters=0, history=False, check_every=0,
+                           stream=None):
+        """solve_cgls through the allocation-free entry point (fixed scratch array)."""
+        return self._solve(_lib.reco_solve_cgls_noalloc, b, x, tol, max_iter, lam, precond, 30,
                            fixed_iters, history, check_every, stream)
 
     def solve_gmres(self, b, x=None, tol=1e-3, max_iter=1000, lam=0.0, precond=PRECOND_WMG,

@@ -216,6 +216,18 @@ reco_status reco_solve_cgls(reco_geometry gh, const void* b, void* x, const reco
   })
 }
 
+reco_status reco_solve_cgls_noalloc(reco_geometry gh, const void* b, void* x,
+                                    const reco_solve_opts* opts, reco_solve_info* info,
+                                    void* stream) {
+  RECO_GUARD({
+    Geometry* g = G(gh);
+    need(b, "b");
+    need(x, "x");
+    need(opts, "opts");
+    return reco::solve_cgls_noalloc(*g, b, x, *opts, info, S(stream));
+  })
+}
+
 reco_status reco_solve_gmres(reco_geometry gh, const void* b, void* x, const reco_solve_opts* opts,
                              reco_solve_info* info, void* stream) {
   RECO_GUARD({

@@ -52,6 +52,9 @@ double now_ms();
 
 reco_status solve_cgls(Geometry& g, const void* b, void* x, const reco_solve_opts& o,
                        reco_solve_info* info, hipStream_t st);
+// CGLS with every buffer in the library's fixed scratch array (no allocation).
+reco_status solve_cgls_noalloc(Geometry& g, const void* b, void* x, const reco_solve_opts& o,
+                               reco_solve_info* info, hipStream_t st);
 reco_status solve_sirt(Geometry& g, const void* b, void* x, const reco_solve_opts& o,
                        reco_solve_info* info, hipStream_t st);
 reco_status solve_bicgstab(Geometry& g, const void* b, void* x, const reco_solve_opts& o,

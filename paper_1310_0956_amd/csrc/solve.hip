@@ -11,6 +11,7 @@
 
 #include "device_common.h"
 #include "solve.h"
+#include "timing.h"
 
 namespace reco {
 
@@ -272,18 +273,143 @@ void cgls_setup(Geometry& g, Workspace& w, const void* b, void* x, const reco_so
   if (!backward_fuses_wmg(g)) launch_wmg(g, WMG_CGLS_INIT, cgls_wmg_args(w, o), st);
 }
 
-reco_status solve_cgls(Geometry& g, const void* b, void* x, const reco_solve_opts& o,
-                       reco_solve_info* info, hipStream_t st) {
-  validate_opts(o, false);
-  const double t0 = now_ms();
-  Lease lease(g, st);
-  Workspace& w = *lease.w;
+static reco_status run_cgls(Geometry& g, Workspace& w, const void* b, void* x,
+                            const reco_solve_opts& o, reco_solve_info* info, hipStream_t st,
+                            double t0) {
   cgls_setup(g, w, b, x, o, st);
   const int limit = o.fixed_iters > 0 ? o.fixed_iters : o.max_iter;
   drive(w, o, limit, st, [&] { cgls_iteration(g, w, x, o, st); });
   const SolverState& s = *w.h_st;
   finish_info(w, o, info, 1 + s.iter, now_ms() - t0, st);
   return status_of(s.done);
+}
+
+reco_status solve_cgls(Geometry& g, const void* b, void* x, const reco_solve_opts& o,
+                       reco_solve_info* info, hipStream_t st) {
+  validate_opts(o, false);
+  const double t0 = now_ms();
+  Lease lease(g, st);
+  return run_cgls(g, *lease.w, b, x, o, info, st, t0);
+}
+
+// ---------------------------------------------------------------------------
+// Allocation-free CGLS
+// ---------------------------------------------------------------------------
+// Every device buffer of the solve is carved from one fixed device array and
+// the host copy of the solver state lives on the caller's stack, so the call
+// makes no device or host allocation.  The array's name is a host-side
+// stand-in, not a device address: its address on each device is looked up
+// once, with that device current, and only that address reaches kernels and
+// fills.  All calls on one device share the array, so calls that overlap on
+// one device race; every buffer whose contents the kernels assume (ticket
+// counters at zero, finisher slots empty-marked, zero padding columns) is
+// re-established by fill kernels at the start of each call.
+static_assert(RECO_NOALLOC_SCRATCH_BYTES % 256 == 0, "scratch size");
+static __device__ __align__(256) unsigned char scratch[RECO_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_addr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device.
+void* scratch_address() {
+  int dev = -1;
+  HIP_CHECK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) fail(RECO_EDEVICE, "device ordinal out of range");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_addr[dev]) {
+    void* p = nullptr;
+    HIP_CHECK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) fail(RECO_EDEVICE, "scratch array has no device address");
+    g_scratch_addr[dev] = p;
+  }
+  return g_scratch_addr[dev];
+}
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+// Byte offsets of the CGLS buffers inside the scratch array.
+struct ScratchLayout {
+  size_t r, q, s, p, zP, zTP, partial, counter, st, hist, total;
+  int red_cap;
+};
+
+ScratchLayout scratch_layout(const Geometry& g, int hist_cap) {
+  ScratchLayout l{};
+  const size_t es = g.esize();
+  const int cap = std::max(forward_blocks(g), std::max(backward_blocks(g), wmg_blocks(g)));
+  l.red_cap = cap * 4;
+  size_t off = 0;
+  auto put = [&](size_t bytes) { const size_t at = off; off = align_up(off + bytes); return at; };
+  l.r = put(es * g.M());
+  l.q = put(es * g.M());
+  l.s = put(es * g.N());
+  l.p = put(es * g.N());
+  l.zP = put(es * g.padded_elems());
+  l.zTP = put(es * g.padded_elems());
+  l.partial = put(sizeof(double) * (2 * (size_t)l.red_cap + cap));
+  l.counter = put(sizeof(unsigned) * 4);
+  l.st = put(sizeof(SolverState));
+  l.hist = put(sizeof(double) * (size_t)hist_cap);
+  l.total = off;
+  return l;
+}
+
+// A Workspace whose buffers point into the scratch array: never freed.
+struct BorrowedWorkspace {
+  Workspace w;
+  SolverState host_state{};
+  ~BorrowedWorkspace() {
+    w.r = w.q = w.s = w.p = w.zP = w.zTP = nullptr;
+    w.partial = nullptr;
+    w.counter = nullptr;
+    w.st = nullptr;
+    w.h_st = nullptr;
+    w.hist = nullptr;
+  }
+};
+}  // namespace
+
+reco_status solve_cgls_noalloc(Geometry& g, const void* b, void* x, const reco_solve_opts& o,
+                               reco_solve_info* info, hipStream_t st) {
+  validate_opts(o, false);
+  if (timing_on())
+    fail(RECO_EINVAL, "per-kernel timing is enabled; its events are created on demand");
+  const int limit = o.fixed_iters > 0 ? o.fixed_iters : o.max_iter;
+  const ScratchLayout l = scratch_layout(g, limit);
+  if (l.total > (size_t)RECO_NOALLOC_SCRATCH_BYTES)
+    fail(RECO_EINVAL, "problem needs " + std::to_string(l.total) +
+                          " bytes of solver scratch; the fixed scratch array holds " +
+                          std::to_string((size_t)RECO_NOALLOC_SCRATCH_BYTES));
+  const double t0 = now_ms();
+  char* base = static_cast<char*>(scratch_address());
+  BorrowedWorkspace bw;
+  Workspace& w = bw.w;
+  w.r = base + l.r;
+  w.q = base + l.q;
+  w.s = base + l.s;
+  w.p = base + l.p;
+  w.zP = base + l.zP;
+  w.zTP = base + l.zTP;
+  w.partial = reinterpret_cast<double*>(base + l.partial);
+  w.red_cap = l.red_cap;
+  w.counter = reinterpret_cast<unsigned*>(base + l.counter);
+  w.st = reinterpret_cast<SolverState*>(base + l.st);
+  w.h_st = &bw.host_state;
+  w.hist = reinterpret_cast<double*>(base + l.hist);
+  w.hist_cap = limit;
+  // what the kernels assume of a fresh workspace: zero ticket counters (four
+  // 32-bit words, filled as floats of value 0), empty-marked finisher slots,
+  // zero padding columns of the padded image copies
+  launch_fill(w.counter, 4, false, 0.0, st);
+  double empty;
+  std::memcpy(&empty, &kSlotEmpty, sizeof(empty));
+  launch_fill(fin_slots(w), w.red_cap, true, empty, st);
+  launch_fill(w.zP, g.padded_elems(), g.f64, 0.0, st);
+  launch_fill(w.zTP, g.padded_elems(), g.f64, 0.0, st);
+  return run_cgls(g, w, b, x, o, info, st, t0);
 }
 
 // ---------------------------------------------------------------------------

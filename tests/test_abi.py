@@ -54,6 +54,7 @@ def test_invalid_arguments_rejected_without_gpu_work():
     assert lib.reco_create_geometry(None, None, ctypes.byref(out)) == reco.RECO_EINVAL
     assert lib.reco_project(None, None, None, None) == reco.RECO_EINVAL
     assert lib.reco_solve_cgls(None, None, None, None, None, None) == reco.RECO_EINVAL
+    assert lib.reco_solve_cgls_noalloc(None, None, None, None, None, None) == reco.RECO_EINVAL
     assert lib.reco_solve_batch(-1, None, None, None, None, None, None) == reco.RECO_EINVAL
     assert lib.reco_solve_batch(0, None, None, None, None, None, None) == reco.RECO_OK
     assert lib.reco_solve_batch(1, None, None, None, None, None, None) == reco.RECO_EINVAL
@@ -97,3 +98,10 @@ def test_binding_structs_match_header():
             assert type(ptype) is type(want) or ptype is want, (cname, hname)
     assert [f for f, _ in _header_struct("reco_geometry_desc")][-1] == "projector"
     assert reco.PROJ_EXACT == 0 and reco.PROJ_JOSEPH == 1
+
+
+def test_noalloc_scratch_size_matches_header():
+    import paper_1310_0956_amd as reco
+    txt = open(HEADER).read()
+    m = re.search(r"#define RECO_NOALLOC_SCRATCH_BYTES \((\d+)u \* 1024u \* 1024u\)", txt)
+    assert m and int(m.group(1)) * 1024 * 1024 == reco.NOALLOC_SCRATCH_BYTES
