@@ -51,6 +51,31 @@ def phantom_and_data(n, m, nb, n_ellipses, seed, noise=0.0, dtype64=False):
     return x, b
 
 
+def f32_store(eps, seed):
+    """Float32 storage model for the oracle's kept vectors: a relative Gaussian
+    error of size eps (a measured operator error), then rounding to float32."""
+    g = np.random.default_rng(seed)
+    return lambda v: (v * (1.0 + eps * g.standard_normal(np.shape(v)))).astype(
+        np.float32).astype(np.float64)
+
+
+def f32_envelope(run, ref_x, eps, seeds=5):
+    """Largest deviation of an oracle run from ref_x under the float32 storage
+    model (run(store) returns the oracle's result with that store hook)."""
+    return max(rel(run(f32_store(eps, 100 + s)).x, ref_x) for s in range(seeds))
+
+
+def operator_eps(g, W, x, y):
+    """Relative L2 error of a float32 GPU geometry's projector and backprojector
+    against the oracle's W and W^T (on the values the GPU sees)."""
+    import torch
+    xs, ys = to_gpu(x, torch.float32), to_gpu(y, torch.float32)
+    x_dev, y_dev = to_np(xs).ravel(), to_np(ys).ravel()
+    e_fwd = rel(to_np(g.project(xs)), W @ x_dev)
+    e_bwd = rel(to_np(g.backproject(ys)), W.T @ y_dev)
+    return e_fwd, e_bwd
+
+
 def check_diag_elementwise(d, d_ref, tol):
     """Every packet coefficient within tol of its own oracle value."""
     d = np.asarray(d, dtype=np.float64).ravel()

@@ -1,9 +1,13 @@
-"""Batched solves and the server against solo solves of the same problems.
+"""Batched solves and the server against solo solves of the same problems and
+against the float64 oracle.
 
 A batched launch runs each problem's blocks with that problem's own arguments,
 state and reduction scratch, in the same per-problem order as the solo kernels,
-so every result must equal the solo reco_solve_cgls result bit for bit (the
-solo path itself is checked against the float64 oracle in the solver tests).
+so every result must equal the solo reco_solve_cgls result bit for bit.  A
+seeded subset of problems (sides 64-256, 2-3 WMG levels, one Tikhonov and one
+unpreconditioned problem) is also compared with the oracle's PCGLS at the
+iteration count the GPU stopped at, within 3x the oracle's float32 envelope at
+each geometry's measured operator error (the float32 bar of the solver tests).
 """
 import time
 
@@ -11,7 +15,9 @@ import numpy as np
 import pytest
 
 import inputs
-from gpu_common import print_case
+from gpu_common import (f32_envelope, oracle_W, oracle_d, operator_eps, phantom_and_data,
+                        print_case, rel, to_gpu, to_np)
+from oracle import solvers, wmg
 
 torch = pytest.importorskip("torch")
 reco = pytest.importorskip("paper_1310_0956_amd")
@@ -263,3 +269,54 @@ def test_server_invalid_submit():
         assert e.value.status == reco.RECO_ENOTFOUND
     finally:
         srv.close()
+
+
+# (n, m, nb, levels, precond, lambda, tol): oracle-checked subset
+ORACLE_SET = [(64, 90, 91, 2, reco.PRECOND_WMG, 0.0, 1e-3),
+              (128, 90, 182, 3, reco.PRECOND_WMG, 0.5, 1e-3),
+              (128, 180, 182, 2, reco.PRECOND_NONE, 0.0, 1e-3),
+              (256, 180, 363, 3, reco.PRECOND_WMG, 0.0, 1e-2)]
+
+
+def _oracle_check(label, problems, bs_np, xs, iters):
+    for (n, m, nb, lv, pre, lam, tol), b, x, K in zip(problems, bs_np, xs, iters):
+        W = oracle_W(n, m, nb)
+        M = None
+        if pre == reco.PRECOND_WMG:
+            d = oracle_d(n, m, nb, lv - 1) + lam
+            M = (lambda dd, L: (lambda v: wmg.apply_additive_diag(v, dd, L)))(d, lv - 1)
+        refK = solvers.pcgls(W, b, fixed_iters=K, lam=lam, precond=M)
+        g = reco.Geometry(n, m, nb, lv, reco.F32)
+        e_fwd, e_bwd = operator_eps(g, W, np.random.default_rng(n).random((n, n)), b.reshape(m, nb))
+        eps = max(e_fwd, e_bwd)
+        env = f32_envelope(lambda h: solvers.pcgls(W, b, fixed_iters=K, lam=lam, precond=M,
+                                                   store=h), refK.x, eps)
+        dev = rel(to_np(x), refK.x)
+        print(f"{label} {n}x{n} {m}x{nb} lv {lv} precond {pre} lam {lam}: K {K} dev {dev:.3e} "
+              f"eps {eps:.3e} envelope {env:.3e}", flush=True)
+        assert dev <= 3 * env
+
+
+def test_batch_and_server_results_match_oracle():
+    print_case("batch and server vs oracle")
+    bs_np, bs = [], []
+    for i, (n, m, nb, lv, pre, lam, tol) in enumerate(ORACLE_SET):
+        _, b = phantom_and_data(n, m, nb, 6 + i, 7700 + i, noise=0.01)
+        bs_np.append(b)
+        bs.append(to_gpu(b.reshape(m, nb), torch.float32))
+    gs = _geoms([p[:4] for p in ORACLE_SET])
+    xs = [g.new_image() for g in gs]
+    infos = reco.solve_batch(gs, bs, xs, tol=[p[6] for p in ORACLE_SET],
+                             lam=[p[5] for p in ORACLE_SET], precond=[p[4] for p in ORACLE_SET])
+    assert all(i["status"] == "ok" for i in infos), infos
+    _oracle_check("batched", ORACLE_SET, bs_np, xs, [i["iters"] for i in infos])
+    srv = reco.Server(8 << 30, max_slots=16)
+    try:
+        xs2 = [g.new_image() for g in gs]
+        tickets = [srv.submit(n, m, nb, lv, b, x, tol=tol, precond=pre, lam=lam)
+                   for (n, m, nb, lv, pre, lam, tol), b, x in zip(ORACLE_SET, bs, xs2)]
+        res = _wait(srv, tickets)
+    finally:
+        srv.close()
+    assert all(res[t]["status"] == "ok" for t in tickets)
+    _oracle_check("served", ORACLE_SET, bs_np, xs2, [res[t]["iters"] for t in tickets])

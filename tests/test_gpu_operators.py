@@ -125,7 +125,9 @@ def test_project_ct512_full():
 
 
 def test_ct2048_sampled():
-    """2048^2, 2048 angles, 2897 bins at full size: sampled rays, pixels and tiles."""
+    """2048^2, 2048 angles, 2897 bins, 5 WMG levels at full size: sampled rays
+    and pixels of W and W^T, and the packet diagonal and WMG apply on sampled
+    16x16 packet tiles."""
     n, m, nb, lv = 2048, 2048, 2897, 5
     print_case("ct2048 sampled operators")
     og = OG(n, m, nb)
@@ -151,3 +153,27 @@ def test_ct2048_sampled():
         ref = col @ y64
         # rounding bound: 1e-5 of the sum of |terms|
         assert abs(bt[pix] - ref) <= 1e-5 * (np.abs(col) @ np.abs(y64)), pix
+    # packet diagonal and WMG apply on sampled 16x16 packet tiles (L = 4: each
+    # coefficient is a Walsh pattern on one tile, so a tile's coefficients need
+    # only the tile's 256 columns of W; a coefficient at local quadrant-layout
+    # position (r, c) sits at (n/16 r + tile row, n/16 c + tile column) of the
+    # whole image's quadrant layout)
+    import scipy.sparse as sp
+    d_gpu = g.packet_diagonal()
+    s_img = rng.standard_normal((n, n)).astype(np.float32)
+    z_gpu = to_np(g.wmg_apply(to_gpu(s_img, torch.float32))).reshape(n, n)
+    T, S = 16, n // 16
+    for ty, tx in [(0, 0), (57, 83)]:
+        cols = []
+        for iy in range(T):
+            for ix in range(T):
+                cols.append(sp.csr_matrix(pixel_column(og, (ty * T + iy) * n + tx * T + ix)).T)
+        Wt = sp.hstack(cols).tocsr()                     # M x 256, local pixel order
+        d_loc = wmg.packet_diagonal(Wt, T, 4)
+        d_tile = d_gpu[ty::S, tx::S]                     # the tile's coefficients, local layout
+        check_diag_elementwise(d_tile, d_loc, 1e-5)
+        s_tile = s_img[ty * T:(ty + 1) * T, tx * T:(tx + 1) * T].astype(np.float64)
+        z_ref = wmg.apply_additive_diag(s_tile, d_loc, 4)
+        z_tile = z_gpu[ty * T:(ty + 1) * T, tx * T:(tx + 1) * T]
+        print("ct2048 tile", ty, tx, "wmg apply rel err", rel(z_tile, z_ref), flush=True)
+        assert rel(z_tile, z_ref) <= 1e-5

@@ -7,25 +7,28 @@ float64-rounding envelope (the oracle perturbed by relative 2^-53 errors in the
 vectors it keeps, several seeds; that envelope itself reaches 1e-4 there).
 
 Float32 path (float32 projectors and vectors, float64 scalars and reductions):
-CGLS on these noisy normal equations amplifies any white relative perturbation
-of the residual (one float32 rounding, 6e-8) by ~10x per iteration from about
-the 6th iteration on, transiently up to a few percent of the iterate; the
-oracle itself shows the same spread when the vectors it keeps carry float32-
-size errors.  A float32 projection adds up to ~n terms, so its outputs carry
-relative rounding errors of about sqrt(n) * 2^-24 rather than 2^-24; the
-envelope models that (the oracle's kept vectors perturbed by relative
-sqrt(n) * 2^-24, largest deviation over several seeds, at the same iteration
-count).  The float32 tests therefore check (a) early iterates to 1e-5, (b) the
-iterate at the stopping iteration against the oracle within 3x that envelope
-or 1e-4, (c) the same reconstruction error against the true image, and (d)
-stopping within 2 iterations of the oracle.
+CG on these noisy normal equations amplifies perturbations of its vectors by
+~10x per iteration from about the 6th iteration on.  The float64 oracle run
+with every kept vector rounded to float32 (and nothing else changed) already
+moves by 3.2e-2 at the 14th WMG-CGLS iteration of the 512^2 case, so no
+float32-storage implementation can hold 1e-4 there; that figure is met by the
+float64 instantiation only.  The float32 bar is an envelope measured on the
+oracle: at the test's geometry the GPU projector's and backprojector's
+relative error against the oracle's W and W^T is measured first (eps); the
+oracle is then rerun with every kept vector given a relative Gaussian error of
+size eps and rounded to float32, over five seeds, at the GPU's iteration
+count K, and the GPU iterate must lie within 3x the largest deviation seen.
+The tests also check (a) early iterates to 1e-5, (c) the same reconstruction
+error against the true image within 10%, and (d) stopping within 2 iterations
+of the oracle, and print K, the deviation, eps and the envelope.
 """
 import math
 
 import numpy as np
 import pytest
 
-from gpu_common import oracle_W, oracle_d, phantom_and_data, print_case, rel, to_gpu, to_np
+from gpu_common import (f32_envelope, oracle_W, oracle_d, operator_eps, phantom_and_data, print_case,
+                        rel, to_gpu, to_np)
 from oracle import solvers, wmg
 
 torch = pytest.importorskip("torch")
@@ -55,10 +58,6 @@ def _envelope(run, ref_x, eps, seeds=3):
 
 F32_EPS, F64_EPS = 2.0 ** -24, 2.0 ** -53
 
-
-def _op_eps(n):
-    """Relative rounding of a float32 projection output: sums of ~n terms."""
-    return math.sqrt(n) * F32_EPS
 
 def test_tiny64_f64_fifty_iterations():
     """64^2, 90 angles x 64 bins, 10 ellipses, noiseless, float64: SIRT, CGLS, WMG-CGLS x 50."""
@@ -143,6 +142,8 @@ def test_ct512_f32_cgls(ct512, precond):
     M = _minv(oracle_d(n, m, nb, lv - 1), lv - 1) if precond else None
     g = reco.Geometry(n, m, nb, lv, reco.F32)
     bg = to_gpu(b.reshape(m, nb), torch.float32)
+    e_fwd, e_bwd = operator_eps(g, W, x_true, b.reshape(m, nb))
+    eps = max(e_fwd, e_bwd)
     # (a) early iterates
     x5, _ = g.solve_cgls(bg, fixed_iters=5, precond=precond)
     assert rel(to_np(x5), solvers.pcgls(W, b, fixed_iters=5, precond=M).x) <= 1e-5
@@ -151,13 +152,14 @@ def test_ct512_f32_cgls(ct512, precond):
     x, info = g.solve_cgls(bg, tol=1e-3, precond=precond)
     K = info["iters"]
     assert info["status"] == "ok" and abs(K - ref.iters) <= 2
-    # (b) iterate at K within 3x the oracle's own float32-projection envelope
+    # (b) iterate at K within 3x the oracle's float32 envelope at the measured operator error
     refK = solvers.pcgls(W, b, fixed_iters=K, precond=M)
-    spread = _envelope(lambda h: solvers.pcgls(W, b, fixed_iters=K, precond=M, store=h), refK.x,
-                       _op_eps(n))
+    spread = f32_envelope(lambda h: solvers.pcgls(W, b, fixed_iters=K, precond=M, store=h),
+                           refK.x, eps)
     dev = rel(to_np(x), refK.x)
-    print("K", K, "oracle K", ref.iters, "dev", dev, "oracle f32 envelope", spread, flush=True)
-    assert dev <= max(3 * spread, 1e-4)
+    print(f"ct512 f32 cgls precond={precond}: K {K} (oracle {ref.iters}) dev {dev:.3e} "
+          f"operator eps fwd {e_fwd:.3e} bwd {e_bwd:.3e} envelope {spread:.3e}", flush=True)
+    assert dev <= 3 * spread
     # (c) reconstruction quality
     e_gpu, e_ref = rel(to_np(x), x_true), rel(refK.x, x_true)
     assert abs(e_gpu - e_ref) <= 0.1 * e_ref
@@ -170,16 +172,19 @@ def test_ct512_f32_wmg_gmres(ct512):
     W = oracle_W(n, m, nb)
     M = _minv(oracle_d(n, m, nb, lv - 1), lv - 1)
     g = reco.Geometry(n, m, nb, lv, reco.F32)
+    e_fwd, e_bwd = operator_eps(g, W, x_true, b.reshape(m, nb))
+    eps = max(e_fwd, e_bwd)
     x, info = g.solve_gmres(to_gpu(b.reshape(m, nb), torch.float32), tol=1e-3, restart=30)
     K = info["iters"]
     ref = solvers.gmres_right(W, b, tol=1e-3, restart=30, precond=M)
     assert info["status"] == "ok" and abs(K - ref.iters) <= 2
     refK = solvers.gmres_right(W, b, fixed_iters=K, restart=30, precond=M)
-    spread = _envelope(lambda h: solvers.gmres_right(W, b, fixed_iters=K, restart=30, precond=M,
-                                                     store=h), refK.x, _op_eps(n))
+    spread = f32_envelope(lambda h: solvers.gmres_right(W, b, fixed_iters=K, restart=30,
+                                                         precond=M, store=h), refK.x, eps)
     dev = rel(to_np(x), refK.x)
-    print("K", K, "dev", dev, "oracle f32 envelope", spread, flush=True)
-    assert dev <= max(3 * spread, 1e-4)
+    print(f"ct512 f32 wmg-gmres30: K {K} (oracle {ref.iters}) dev {dev:.3e} operator eps "
+          f"fwd {e_fwd:.3e} bwd {e_bwd:.3e} envelope {spread:.3e}", flush=True)
+    assert dev <= 3 * spread
 
 
 def test_ct512_sirt_fixed(ct512):
