@@ -131,11 +131,17 @@ class WaveletCycle:
     def __init__(self, K: np.ndarray, n: int, L: int, mode: str = "hybrid"):
         assert mode in ("multiplicative", "hybrid", "additive")
         self.n, self.L, self.mode = n, L, mode
+        self._leaves = []
         self.tree = self._build(np.asarray(K, dtype=np.float64), n, L)
+        scale = max(float(np.diag(A).max()) for A, _ in self._leaves)
+        for A, slot in self._leaves:
+            slot.append(coarsest_factor(A, scale))
 
     def _build(self, A, s, levels):
         if levels == 0:
-            return ("leaf", sla.cho_factor(A, lower=True))
+            slot = []                  # filled with the factor once all leaves are known
+            self._leaves.append((A, slot))
+            return ("leaf", slot)
         ops = haar.step_operators_2d(s)
         kids = {}
         for name in self.ORDER:
@@ -145,7 +151,7 @@ class WaveletCycle:
 
     def _cycle(self, node, r):
         if node[0] == "leaf":
-            return sla.cho_solve(node[1], r)
+            return coarsest_solve(node[1][0], r)
         _, A, kids = node
         e = np.zeros_like(r)
         if self.mode == "multiplicative":
@@ -167,3 +173,131 @@ class WaveletCycle:
 
     def __call__(self, r):
         return self._cycle(self.tree, np.asarray(r, dtype=np.float64).ravel())
+
+
+# ---------------------------------------------------------------------------
+# Exact coarsest solves with unseen directions
+# ---------------------------------------------------------------------------
+# A coarsest Galerkin block A = (W V)^T (W V) + lam I is only positive
+# semi-definite when lam = 0: a basis function that no ray sees has a zero
+# row and column, and with few rays the seen ones can be linearly dependent.
+# Reading (the paper's Cholesky solve, Section 4.1, on a singular block; the
+# 1/0 := 0 rule of the diagonal case extended): the block is factored by
+# Cholesky in its natural order, and an unknown whose pivot (the diagonal of
+# the remaining Schur complement) is at most DROP_REL times the block's
+# largest diagonal entry is dropped: its column is not eliminated and its
+# correction is zero.  For a positive semi-definite block such a column of
+# the Schur complement is zero up to rounding, so for r in the range of A the
+# result still solves A e = r.  With no pivot dropped this is the plain
+# Cholesky solve.  The threshold is relative to the largest diagonal entry of
+# all coarsest blocks of the hierarchy (`scale`): the rounding that forming a
+# block leaves in it is relative to the operator K, not to that block.
+DROP_REL = 1e-12
+
+
+def coarsest_factor(A: np.ndarray, scale: float | None = None):
+    """(kept mask, lower Cholesky factor of the kept unknowns) of a Galerkin block;
+    pivots at most DROP_REL * scale (default: the block's largest diagonal) are dropped."""
+    A = np.array(A, dtype=np.float64)
+    c = A.shape[0]
+    if scale is None:
+        scale = float(np.diag(A).max()) if c else 0.0
+    thr = DROP_REL * max(scale, 0.0)
+    try:   # fast path: LAPACK, accepted when it drops nothing
+        Lf = sla.cholesky(A, lower=True)
+        if c == 0 or float((np.diag(Lf) ** 2).min()) > thr:
+            return np.ones(c, dtype=bool), Lf
+    except np.linalg.LinAlgError:
+        pass
+    S = A.copy()                       # Schur complement, updated in place
+    Lm = np.zeros_like(A)
+    keep = np.zeros(c, dtype=bool)
+    for k in range(c):
+        piv = S[k, k]
+        if piv <= thr:
+            continue                   # dropped: not eliminated
+        keep[k] = True
+        col = S[k:, k] / np.sqrt(piv)
+        Lm[k:, k] = col
+        S[k + 1:, k + 1:] -= np.outer(col[1:], col[1:])
+    return keep, Lm[np.ix_(keep, keep)]
+
+
+def coarsest_solve(factor, r: np.ndarray) -> np.ndarray:
+    """e = A^-1 r on the kept unknowns (two triangular solves), 0 on the dropped."""
+    keep, Lk = factor
+    r = np.asarray(r, dtype=np.float64)
+    e = np.zeros_like(r)
+    if keep.any():
+        y = sla.solve_triangular(Lk, r[keep], lower=True)
+        e[keep] = sla.solve_triangular(Lk.T, y, lower=False)
+    return e
+
+
+def subband_restriction(n: int, path) -> sp.csr_matrix:
+    """R_P for a path of subband names, coarsest-level last: the product of the
+    step operators of eq. 1of4 - 4of4 at the successive grid sizes (an
+    (n / 2^l)^2 x n^2 matrix with orthonormal rows)."""
+    R = sp.identity(n * n, format="csr")
+    s = n
+    for name in path:
+        R = (haar.step_operators_2d(s)[name] @ R).tocsr()
+        s //= 2
+    return R
+
+
+class HybridCycle:
+    """The hybrid wavelet multigrid cycle of WaveletCycle(mode="hybrid"),
+    matrix free: the Galerkin operator of a node P of the recursion,
+    A_P = R_P K R_P^T with K = W^T W + lam I (eq. galerkin), is applied as
+    R_P (W^T (W (R_P^T u))) + lam u, and only the coarsest operators are formed
+    (densely, from the sparse W R_P^T) and factored (Cholesky, Section 4.1;
+    unseen directions as in coarsest_factor, relative to the largest diagonal
+    entry of all coarsest blocks).
+
+    cycle(P, r):  P at depth L: e = A_P^-1 r
+                  else: e = R_LL^T cycle(P LL, R_LL r);  r' = r - A_P e;
+                        e += sum over LH, HL, HH of R_id^T cycle(P id, R_id r')
+    with R_id the step operators at the node's grid size (Section 3.1.2, the
+    hybrid variant; recursion of Section 3.1.3)."""
+
+    ORDER = ("LL", "LH", "HL", "HH")
+
+    def __init__(self, W: sp.csr_matrix, n: int, L: int, lam: float = 0.0):
+        self.W, self.WT = W.tocsr(), W.T.tocsr()
+        self.n, self.L, self.lam = n, L, float(lam)
+        self.R = {}
+        blocks = {}
+        self._paths((), 0, blocks)
+        scale = max(float(np.diag(A).max()) for A in blocks.values())
+        self.leaf = {p: coarsest_factor(A, scale) for p, A in blocks.items()}
+
+    def _paths(self, path, depth, blocks):
+        self.R[path] = subband_restriction(self.n, path)
+        if depth == self.L:
+            G = (self.W @ self.R[path].T).tocsc()
+            blocks[path] = (G.T @ G).toarray() + self.lam * np.eye(G.shape[1])
+            return
+        for name in self.ORDER:
+            self._paths(path + (name,), depth + 1, blocks)
+
+    def galerkin_apply(self, path, u):
+        """A_P u = R_P (W^T (W (R_P^T u))) + lam u."""
+        R = self.R[path]
+        return R @ (self.WT @ (self.W @ (R.T @ u))) + self.lam * u
+
+    def _cycle(self, path, r):
+        if len(path) == self.L:
+            return coarsest_solve(self.leaf[path], r)
+        s = self.n >> len(path)
+        ops = haar.step_operators_2d(s)
+        R = ops["LL"]
+        e = R.T @ self._cycle(path + ("LL",), R @ r)
+        r2 = r - self.galerkin_apply(path, e)
+        for name in self.ORDER[1:]:
+            R = ops[name]
+            e = e + R.T @ self._cycle(path + (name,), R @ r2)
+        return e
+
+    def __call__(self, r):
+        return self._cycle((), np.asarray(r, dtype=np.float64).ravel())

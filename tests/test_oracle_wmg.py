@@ -136,7 +136,7 @@ class _HybridWithoutUpdate(wmg.WaveletCycle):
 
     def _cycle(self, node, r):
         if node[0] == "leaf":
-            return sla.cho_solve(node[1], r)
+            return wmg.coarsest_solve(node[1][0], r)
         _, A, kids = node
         R, sub = kids["LL"]
         e = R.T @ self._cycle(sub, R @ r)
@@ -151,7 +151,7 @@ class _HybridHighFirst(wmg.WaveletCycle):
 
     def _cycle(self, node, r):
         if node[0] == "leaf":
-            return sla.cho_solve(node[1], r)
+            return wmg.coarsest_solve(node[1][0], r)
         _, A, kids = node
         e = np.zeros_like(r)
         for name in self.ORDER[1:]:
@@ -244,3 +244,104 @@ def test_recursive_hybrid_two_levels():
     assert np.abs(got - Minv).max() <= 1e-9 * np.abs(Minv).max()
     bad = _cycle_matrix(_HybridWithoutUpdate(A, n, 2, "hybrid"), n * n)
     assert np.abs(bad - Minv).max() > 1e-3 * np.abs(Minv).max()
+
+
+# --- the matrix-free hybrid cycle and unseen coarsest unknowns ---
+
+@pytest.mark.parametrize("n,m,nb,L,lam", [(8, 10, 12, 1, 0.0), (16, 12, 23, 2, 0.0),
+                                          (16, 20, 23, 2, 0.3), (16, 9, 16, 3, 0.05)])
+def test_matrix_free_hybrid_equals_dense_cycle(n, m, nb, L, lam):
+    """HybridCycle (Galerkin operators applied through W and the step
+    operators, coarsest blocks from W R_P^T) equals WaveletCycle(mode="hybrid")
+    built from the dense K."""
+    W = system_matrix(Geometry(n, m, nb))
+    K = (W.T @ W).toarray() + lam * np.eye(n * n)
+    dense = wmg.WaveletCycle(K, n, L, "hybrid")
+    mf = wmg.HybridCycle(W, n, L, lam)
+    rng = np.random.default_rng(21)
+    for _ in range(3):
+        r = rng.standard_normal(n * n)
+        a, b = dense(r), mf(r)
+        assert np.linalg.norm(a - b) <= 1e-12 * np.linalg.norm(a)
+    # the Galerkin apply of a node is R_P K R_P^T
+    R = wmg.subband_restriction(n, ("HL",) * min(L, 1))
+    u = rng.standard_normal(R.shape[0])
+    want = R @ (K @ (R.T @ u))
+    assert np.allclose(mf.galerkin_apply(("HL",) * min(L, 1), u), want, rtol=0, atol=1e-12 * np.abs(want).max())
+
+
+def test_subband_restriction_orthonormal_and_matches_packet_transform():
+    """R_P has orthonormal rows, and R_P x is packet P of the L-level packet
+    transform (quadrant layout) of x."""
+    n, L = 16, 2
+    x = np.random.default_rng(3).standard_normal((n, n))
+    c = haar.packet_transform(x, L)
+    cs = n >> L
+    names = ("LL", "LH", "HL", "HH")
+    q = {"LL": (0, 0), "LH": (0, 1), "HL": (1, 0), "HH": (1, 1)}
+    for a in names:
+        for b in names:
+            R = wmg.subband_restriction(n, (a, b))
+            assert np.allclose((R @ R.T).toarray(), np.eye(cs * cs), atol=1e-14)
+            row = q[a][0] * (n >> 1) + q[b][0] * (n >> 2)
+            col = q[a][1] * (n >> 1) + q[b][1] * (n >> 2)
+            assert np.allclose((R @ x.ravel()).reshape(cs, cs), c[row:row + cs, col:col + cs],
+                               atol=1e-13)
+
+
+def test_coarsest_solve_drops_unseen_unknowns():
+    """A positive semi-definite block (two unseen unknowns, one more that
+    repeats a combination of others): the dropped unknowns get a zero correction,
+    the result solves A e = r for r in the range of A, and with nothing to drop
+    it is the plain Cholesky solve."""
+    rng = np.random.default_rng(5)
+    G = rng.standard_normal((30, 12))
+    G[:, [2, 7]] = 0.0                          # two unseen unknowns
+    G[:, 9] = G[:, 0] - 0.5 * G[:, 4]           # a dependent one (dropped at its pivot)
+    A = G.T @ G
+    keep, Lk = wmg.coarsest_factor(A)
+    assert list(np.nonzero(~keep)[0]) == [2, 7, 9]
+    r = A @ rng.standard_normal(12)              # in the range of A
+    e = wmg.coarsest_solve((keep, Lk), r)
+    assert e[2] == 0.0 and e[7] == 0.0 and e[9] == 0.0
+    assert np.allclose(A @ e, r, atol=1e-10 * np.abs(r).max())
+    B = A + np.eye(12)
+    fac = wmg.coarsest_factor(B)
+    assert fac[0].all()
+    assert np.allclose(wmg.coarsest_solve(fac, r), np.linalg.solve(B, r), rtol=1e-12, atol=1e-12)
+
+
+def test_coarsest_factor_elimination_matches_lapack():
+    """The explicit elimination (used when a pivot is dropped) equals LAPACK's
+    Cholesky on a positive definite block; a planted wrong pivot order fails."""
+    rng = np.random.default_rng(6)
+    G = rng.standard_normal((40, 10))
+    A = G.T @ G
+    A[3, 3] *= 1.0 + 1e-9
+    Lref = np.linalg.cholesky(A)
+    # force the elimination path: one unseen unknown appended
+    A2 = np.zeros((11, 11))
+    A2[:10, :10] = A
+    keep, Lk = wmg.coarsest_factor(A2)
+    assert keep[:10].all() and not keep[10]
+    assert np.allclose(Lk, Lref, rtol=1e-12, atol=1e-12)
+    assert not np.allclose(Lk, np.linalg.cholesky(A[::-1, ::-1]), atol=1e-6)
+
+
+def test_hybrid_cycle_with_unseen_pixels():
+    """Two axis directions with a detector narrower than the image leave its
+    corners unseen (with many angles every pixel is seen at the angle
+    perpendicular to its position): the coarsest blocks are singular, the cycle
+    still runs, dropped unknowns get no correction, and the dense and
+    matrix-free cycles agree."""
+    n, m, nb, L = 16, 2, 9, 2
+    W = system_matrix(Geometry(n, m, nb))
+    assert (np.asarray(abs(W).sum(axis=0)).ravel() == 0).any()   # unseen pixels exist
+    mf = wmg.HybridCycle(W, n, L)
+    assert sum(int((~k).sum()) for k, _ in mf.leaf.values()) > 0
+    K = (W.T @ W).toarray()
+    dense = wmg.WaveletCycle(K, n, L, "hybrid")
+    r = W.T @ np.random.default_rng(9).standard_normal(m * nb)
+    a, b = dense(r), mf(r)
+    assert np.all(np.isfinite(b))
+    assert np.linalg.norm(a - b) <= 1e-10 * np.linalg.norm(a)
