@@ -51,7 +51,10 @@ typedef int32_t reco_status;
 #define RECO_F64 1
 
 #define RECO_PRECOND_NONE 0
-#define RECO_PRECOND_WMG  1
+#define RECO_PRECOND_WMG  1   /* additive WMG, packet-diagonal coarsest solves */
+#define RECO_PRECOND_WMG_HYBRID 2   /* the hybrid WMG cycle with exact coarsest
+                                       solves (GMRES and BiCGStab only; see
+                                       reco_wmg_hybrid_apply) */
 
 /* Projection kernels (reco_geometry_desc.projector). */
 #define RECO_PROJ_EXACT  0   /* exact ray-pixel intersection lengths */
@@ -84,7 +87,8 @@ typedef struct {
  * residual ||W^T (b - W x) - lambda x|| / ||W^T b|| for CGLS and GMRES; the
  * relative size of the last correction for SIRT).  max_iter >= 1.  restart is
  * the GMRES restart length (1..64).  lambda >= 0 is the Tikhonov weight
- * (CGLS/GMRES).  precond is RECO_PRECOND_NONE or RECO_PRECOND_WMG.
+ * (CGLS/GMRES).  precond is RECO_PRECOND_NONE, RECO_PRECOND_WMG or (GMRES and
+ * BiCGStab) RECO_PRECOND_WMG_HYBRID.
  * check_every is the host poll period in iterations (0 = adaptive).
  * history, if not NULL, receives up to history_cap relative residuals (host
  * memory).  fixed_iters > 0 runs exactly that many iterations, ignoring tol. */
@@ -160,6 +164,23 @@ reco_status reco_backproject(reco_geometry g, const void* b, void* x, void* stre
  * r, z: images [n][n]; they may not alias.  Asynchronous. */
 reco_status reco_wmg_apply(reco_geometry g, const void* r, void* z, double lambda,
                            void* stream);
+
+/* z = M^-1 r with the paper's hybrid wavelet multigrid cycle (Section 3.1.2,
+ * hybrid variant, recursed over the wmg_levels - 1 levels of Section 3.1.3)
+ * on K = W^T W + lambda I: at each node of the recursion the LL subproblem is
+ * treated first, the residual is updated with the node's Galerkin operator
+ * (eq. galerkin), and the LH, HL and HH subproblems are treated with that
+ * residual; the coarsest subproblems (one Haar packet over all 2^L x 2^L
+ * tiles) are solved exactly by Cholesky (Section 4.1), the factors being
+ * built in float64 on first use for each lambda and kept with the geometry.
+ * Reading for singular coarsest blocks (unseen pixels, too few rays): pivots
+ * at most 1e-12 of the largest coarsest diagonal entry are dropped (zero
+ * correction).  The cycle is not symmetric, so CGLS rejects it.  Limits:
+ * 2 <= wmg_levels <= 4, at most 4096 unknowns per coarsest block and 8 GiB of
+ * factors (16 n^4 / 4^L bytes), else RECO_EINVAL.  r, z: images [n][n] (no
+ * aliasing).  Synchronous. */
+reco_status reco_wmg_hybrid_apply(reco_geometry g, const void* r, void* z, double lambda,
+                                  void* stream);
 
 /* CGLS on (W^T W + lambda I) x = W^T b (a Krylov method of Section 2.3.1),
  * preconditioned by M^-1 when opts->precond == RECO_PRECOND_WMG.

@@ -22,7 +22,7 @@ RECO_OK, RECO_PENDING, RECO_ENOTCONV = 0, 1, 2
 RECO_EINVAL, RECO_ENOMEM, RECO_EDEVICE, RECO_ENUMERIC, RECO_ENOTFOUND = -1, -2, -3, -4, -5
 F32, F64 = 0, 1
 NOALLOC_SCRATCH_BYTES = 64 * 1024 * 1024   # RECO_NOALLOC_SCRATCH_BYTES
-PRECOND_NONE, PRECOND_WMG = 0, 1
+PRECOND_NONE, PRECOND_WMG, PRECOND_WMG_HYBRID = 0, 1, 2
 PROJ_EXACT, PROJ_JOSEPH = 0, 1   # exact intersection lengths / Joseph's kernel
 STATUS_NAMES = {0: "ok", 1: "pending", 2: "not_converged", -1: "einval", -2: "enomem",
                 -3: "edevice", -4: "enumeric", -5: "enotfound"}
@@ -63,6 +63,7 @@ _sig = {
     "reco_project": (_S, [_P, _P, _P, _P]),
     "reco_backproject": (_S, [_P, _P, _P, _P]),
     "reco_wmg_apply": (_S, [_P, _P, _P, C.c_double, _P]),
+    "reco_wmg_hybrid_apply": (_S, [_P, _P, _P, C.c_double, _P]),
     "reco_solve_cgls": (_S, [_P, _P, _P, C.POINTER(SolveOpts), C.POINTER(SolveInfo), _P]),
     "reco_solve_cgls_noalloc": (_S, [_P, _P, _P, C.POINTER(SolveOpts), C.POINTER(SolveInfo),
                                      _P]),
@@ -225,6 +226,13 @@ class Geometry:
         out = self.new_image() if out is None else out
         _check(_lib.reco_wmg_apply(self.handle, self._img(r, "r"), self._img(out, "z"),
                                    float(lam), _stream(stream)))
+        return out
+
+    def wmg_hybrid_apply(self, r, out=None, lam=0.0, stream=None):
+        """z = M^-1 r with the hybrid wavelet cycle and exact coarsest solves."""
+        out = self.new_image() if out is None else out
+        _check(_lib.reco_wmg_hybrid_apply(self.handle, self._img(r, "r"), self._img(out, "z"),
+                                          float(lam), _stream(stream)))
         return out
 
     def packet_diagonal(self):

@@ -26,6 +26,7 @@ SOURCES = [
     "solve.hip",
     "gmres.hip",
     "bicgstab.hip",
+    "hybrid.hip",
     "batch.hip",
     "abi.hip",
     "timing.hip",

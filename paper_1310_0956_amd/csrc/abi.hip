@@ -5,6 +5,7 @@
 #include <cstring>
 #include <new>
 
+#include "hybrid.h"
 #include "internal.h"
 #include "solve.h"
 
@@ -201,6 +202,30 @@ reco_status reco_wmg_apply(reco_geometry gh, const void* r, void* z, double lamb
     wa.z = z;
     wa.lambda = lambda;
     reco::launch_wmg(*g, reco::WMG_PLAIN, wa, S(stream));
+    return RECO_OK;
+  })
+}
+
+reco_status reco_wmg_hybrid_apply(reco_geometry gh, const void* r, void* z, double lambda,
+                                  void* stream) {
+  RECO_GUARD({
+    Geometry* g = G(gh);
+    need(r, "r");
+    need(z, "z");
+    if (r == z) reco::fail(RECO_EINVAL, "r and z must not alias");
+    if (!(lambda >= 0.0)) reco::fail(RECO_EINVAL, "lambda must be >= 0");
+    const reco::HybridFactors& f = reco::ensure_hybrid(*g, lambda, S(stream));
+    reco::Workspace* w = reco::checkout_workspace(*g, S(stream));
+    try {
+      reco::HybridScratch& s = reco::hybrid_scratch(*g, *w, S(stream));
+      reco::hybrid_apply(*g, f, s, r, nullptr, nullptr, z, S(stream));
+      HIP_CHECK(hipStreamSynchronize(S(stream)));
+    } catch (...) {
+      w->tainted = true;
+      reco::return_workspace(*g, w);
+      throw;
+    }
+    reco::return_workspace(*g, w);
     return RECO_OK;
   })
 }

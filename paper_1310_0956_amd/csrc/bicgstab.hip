@@ -25,6 +25,7 @@
 #include <cmath>
 
 #include "device_common.h"
+#include "hybrid.h"
 #include "solve.h"
 
 namespace reco {
@@ -235,6 +236,9 @@ reco_status bicgstab_impl(Geometry& g, const void* bvoid, void* xvoid, const rec
   double* D = w.gm;
   double *d0 = D, *d1 = D + chunks, *d2 = D + 2 * chunks, *d3 = D + 3 * chunks;
   const bool ident = o.precond == RECO_PRECOND_NONE;
+  const bool hyb = o.precond == RECO_PRECOND_WMG_HYBRID;
+  const HybridFactors* hf = hyb ? &ensure_hybrid(g, o.lambda, st) : nullptr;
+  HybridScratch* hs = hyb ? &hybrid_scratch(g, w, st) : nullptr;
   SolverState* ds = w.st;
   const unsigned gN = grid_of(N);
   launch_state_init(ds, o.tol, limit, fixed ? 1 : 0, o.lambda, w.hist, limit, st);
@@ -258,14 +262,18 @@ reco_status bicgstab_impl(Geometry& g, const void* bvoid, void* xvoid, const rec
   HIP_CHECK(hipGetLastError());
   // M^-1 of `in` into the padded pair (P, TP), then out = K M^-1 in
   auto apply_K = [&](const T* in, void* P, void* TP, T* out) {
-    WmgArgs wa{};
-    wa.s = in;
-    wa.zP = P;
-    wa.zTP = TP;
-    wa.lambda = o.lambda;
-    wa.identity = ident;
-    wa.st = ds;
-    launch_wmg(g, WMG_GMRES, wa, st);
+    if (hyb) {
+      hybrid_apply(g, *hf, *hs, in, P, TP, nullptr, st);
+    } else {
+      WmgArgs wa{};
+      wa.s = in;
+      wa.zP = P;
+      wa.zTP = TP;
+      wa.lambda = o.lambda;
+      wa.identity = ident;
+      wa.st = ds;
+      launch_wmg(g, WMG_GMRES, wa, st);
+    }
     FwdArgs fa{};
     fa.imgP = P;
     fa.imgTP = TP;
@@ -333,7 +341,8 @@ reco_status solve_bicgstab(Geometry& g, const void* b, void* x, const reco_solve
   if (!(o.tol > 0.0) && o.fixed_iters <= 0) fail(RECO_EINVAL, "tol must be > 0");
   if (o.max_iter < 1 && o.fixed_iters <= 0) fail(RECO_EINVAL, "max_iter must be >= 1");
   if (!(o.lambda >= 0.0)) fail(RECO_EINVAL, "lambda must be >= 0");
-  if (o.precond != RECO_PRECOND_NONE && o.precond != RECO_PRECOND_WMG)
+  if (o.precond != RECO_PRECOND_NONE && o.precond != RECO_PRECOND_WMG &&
+      o.precond != RECO_PRECOND_WMG_HYBRID)
     fail(RECO_EINVAL, "unknown preconditioner");
   if (o.history_cap < 0) fail(RECO_EINVAL, "history_cap must be >= 0");
   if (o.check_every < 0) fail(RECO_EINVAL, "check_every must be >= 0");

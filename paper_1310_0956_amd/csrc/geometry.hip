@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstring>
 
+#include "hybrid.h"
 #include "internal.h"
 
 namespace reco {

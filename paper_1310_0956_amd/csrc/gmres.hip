@@ -8,6 +8,7 @@
 #include <cmath>
 
 #include "device_common.h"
+#include "hybrid.h"
 #include "solve.h"
 
 namespace reco {
@@ -257,6 +258,9 @@ reco_status gmres_impl(Geometry& g, const void* bvoid, void* xvoid, const reco_s
   launch_state_init(w.st, o.tol, limit, fixed ? 1 : 0, o.lambda, w.hist, limit, st);
   launch_fill(x, N, g.f64, 0.0, st);
   const bool ident = o.precond == RECO_PRECOND_NONE;
+  const bool hyb = o.precond == RECO_PRECOND_WMG_HYBRID;
+  const HybridFactors* hf = hyb ? &ensure_hybrid(g, o.lambda, st) : nullptr;
+  HybridScratch* hs = hyb ? &hybrid_scratch(g, w, st) : nullptr;
   // f = W^T b ; v0 = f / ||f||
   {
     BwdArgs ba{};
@@ -281,14 +285,18 @@ reco_status gmres_impl(Geometry& g, const void* bvoid, void* xvoid, const reco_s
     for (int j = 0; j < R && total < limit; ++j) {
       T* vj = V + (size_t)j * N;
       T* wv = V + (size_t)(j + 1) * N;
-      WmgArgs wa{};
-      wa.s = vj;
-      wa.zP = w.zP;
-      wa.zTP = w.zTP;
-      wa.lambda = o.lambda;
-      wa.identity = ident;
-      wa.st = w.st;
-      launch_wmg(g, WMG_GMRES, wa, st);
+      if (hyb) {
+        hybrid_apply(g, *hf, *hs, vj, w.zP, w.zTP, nullptr, st);
+      } else {
+        WmgArgs wa{};
+        wa.s = vj;
+        wa.zP = w.zP;
+        wa.zTP = w.zTP;
+        wa.lambda = o.lambda;
+        wa.identity = ident;
+        wa.st = w.st;
+        launch_wmg(g, WMG_GMRES, wa, st);
+      }
       FwdArgs fa{};
       fa.imgP = w.zP;
       fa.imgTP = w.zTP;
@@ -338,7 +346,9 @@ reco_status gmres_impl(Geometry& g, const void* bvoid, void* xvoid, const reco_s
     hipLaunchKernelGGL(k_backsub, dim3(1), dim3(1), 0, st, gm, lay, (const SolverState*)w.st);
     hipLaunchKernelGGL(k_lincomb<T>, dim3(grid1(N)), dim3(256), 0, st, V, u, N,
                        (const double*)lay.y(gm), (const SolverState*)w.st);
-    {
+    if (hyb) {
+      hybrid_apply(g, *hf, *hs, u, nullptr, nullptr, w.s, st);
+    } else {
       WmgArgs wa{};
       wa.s = u;
       wa.z = w.s;
@@ -403,7 +413,8 @@ reco_status solve_gmres(Geometry& g, const void* b, void* x, const reco_solve_op
   if (o.max_iter < 1 && o.fixed_iters <= 0) fail(RECO_EINVAL, "max_iter must be >= 1");
   if (o.restart < 1 || o.restart > 64) fail(RECO_EINVAL, "restart must be in [1, 64]");
   if (!(o.lambda >= 0.0)) fail(RECO_EINVAL, "lambda must be >= 0");
-  if (o.precond != RECO_PRECOND_NONE && o.precond != RECO_PRECOND_WMG)
+  if (o.precond != RECO_PRECOND_NONE && o.precond != RECO_PRECOND_WMG &&
+      o.precond != RECO_PRECOND_WMG_HYBRID)
     fail(RECO_EINVAL, "unknown preconditioner");
   const auto t0 = std::chrono::steady_clock::now();
   Workspace* w = checkout_workspace(g, st);

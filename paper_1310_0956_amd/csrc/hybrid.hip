@@ -1,0 +1,598 @@
+// The hybrid wavelet multigrid cycle with exact coarsest solves (Section
+// 3.1.2, hybrid variant; recursion of Section 3.1.3; Cholesky coarsest solves
+// of Section 4.1), used as a right preconditioner by BiCGStab and GMRES.
+//
+// Coefficient layout: the L-level full Haar packet transform of an image is
+// the tile-local 2D Walsh-Hadamard transform of its 2^L x 2^L tiles, scaled by
+// 2^-L; the coefficient of packet (py, px) of tile (ty, tx) sits at pixel
+// (ty 2^L + py, tx 2^L + px).  Bit l of py (px) is the band (0 low, 1 high)
+// along y (x) at level l + 1, so the subproblems of depth l of the recursion
+// are the sets of positions whose local index has given low l bits: node P =
+// (cy, cx) at depth l owns the positions with (py, px) mod 2^l = (cy, cx), its
+// LL child the ones with bit l of both zero, LH bit l of px set, HL of py, HH
+// of both.  The Galerkin operator of node P, R_P K R_P^T with
+// K = W^T W + lambda I, is applied on the fine grid: the node's vector is
+// synthesised into an image, projected, backprojected (plus lambda times the
+// image) and analysed again.  The coarsest problems (one packet over all
+// tiles, c = (n / 2^L)^2 unknowns) are solved with the inverse Cholesky
+// factors built at set-up: A_p^-1 = X^T X, X = L^-1.
+//
+// The cycle on node P with residual r (coefficients on P's positions):
+//   depth L:  e = A_P^-1 r
+//   else:     e_LL = cycle(P LL, r);  r' = r - A_P e_LL  (on the LH, HL, HH
+//             positions);  e_id = cycle(P id, r') for id = LH, HL, HH.
+//
+// Set-up (float64, on a float64 copy of the geometry): A_p[i][j] is the
+// packet-p coefficient of tile j of K v_i, v_i the packet-p basis image of tile
+// i (its Walsh pattern times 2^-L), one Galerkin apply per unknown; then a
+// Cholesky factorisation of every block in natural order in which pivots at
+// most 1e-12 of the largest coarsest diagonal entry are dropped (not
+// eliminated; zero correction), then X = L^-1 row by row and its transpose.
+#include <cmath>
+#include <map>
+#include <memory>
+
+#include "device_common.h"
+#include "hybrid.h"
+#include "solve.h"
+
+namespace reco {
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// Tile-local Walsh-Hadamard transform (orthonormal; its own inverse)
+// ---------------------------------------------------------------------------
+struct WhtArgs {
+  const void* src;
+  int src_ld, src_off;           // source [n][src_ld], image column 0 at src_off
+  void* dst;
+  int dst_ld, dst_off;
+  void* dstT;                    // transposed copy (same ld / offset), may be null
+  const void* base;              // subtract mode: dst = base - transform
+  int n, tiles;
+  int in_depth, in_cy, in_cx;    // input mask: keep positions with this prefix (depth 0: all)
+  int sub;                       // subtract mode on the positions with prefix
+  int out_depth, out_cy, out_cx; // (out_depth, out_c) except its LL child's
+};
+
+template <typename T, int TS>
+__global__ __launch_bounds__(256) void k_tile_wht(WhtArgs a) {
+  const int tile = blockIdx.x * 256 + threadIdx.x;
+  if (tile >= a.tiles * a.tiles) return;
+  const int ty = tile / a.tiles, tx = tile - ty * a.tiles;
+  const T* __restrict__ src = (const T*)a.src;
+  const int mi = (1 << a.in_depth) - 1;
+  T v[TS][TS];
+#pragma unroll
+  for (int qy = 0; qy < TS; ++qy) {
+#pragma unroll
+    for (int qx = 0; qx < TS; ++qx) {
+      const size_t iy = (size_t)ty * TS + qy, ix = (size_t)tx * TS + qx;
+      T val = src[iy * a.src_ld + a.src_off + ix];
+      if ((qy & mi) != a.in_cy || (qx & mi) != a.in_cx) val = T(0);
+      v[qy][qx] = val;
+    }
+  }
+#pragma unroll
+  for (int b = 1; b < TS; b <<= 1) {
+#pragma unroll
+    for (int qy = 0; qy < TS; ++qy) {
+#pragma unroll
+      for (int qx = 0; qx < TS; ++qx) {
+        if (qx & b) continue;
+        const T u = v[qy][qx], w = v[qy][qx | b];
+        v[qy][qx] = u + w;
+        v[qy][qx | b] = u - w;
+      }
+    }
+  }
+#pragma unroll
+  for (int b = 1; b < TS; b <<= 1) {
+#pragma unroll
+    for (int qy = 0; qy < TS; ++qy) {
+      if (qy & b) continue;
+#pragma unroll
+      for (int qx = 0; qx < TS; ++qx) {
+        const T u = v[qy][qx], w = v[qy | b][qx];
+        v[qy][qx] = u + w;
+        v[qy | b][qx] = u - w;
+      }
+    }
+  }
+  const T scale = T(1) / T(TS);   // 2^-L, exact
+  T* __restrict__ dst = (T*)a.dst;
+  T* __restrict__ dstT = (T*)a.dstT;
+  const T* __restrict__ base = (const T*)a.base;
+  const int mo = (1 << a.out_depth) - 1, hb = 1 << a.out_depth;
+#pragma unroll
+  for (int qy = 0; qy < TS; ++qy) {
+#pragma unroll
+    for (int qx = 0; qx < TS; ++qx) {
+      const size_t iy = (size_t)ty * TS + qy, ix = (size_t)tx * TS + qx;
+      const T val = v[qy][qx] * scale;
+      if (!a.sub) {
+        dst[iy * a.dst_ld + a.dst_off + ix] = val;
+        if (dstT) dstT[ix * a.dst_ld + a.dst_off + iy] = val;
+      } else if ((qy & mo) == a.out_cy && (qx & mo) == a.out_cx && ((qy & hb) | (qx & hb))) {
+        dst[iy * a.n + ix] = base[iy * a.n + ix] - val;
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Coarsest solves: y = X r_p (gathered from a coefficient image), then
+// e_p = XT y (scattered into one), for up to three packets per launch.
+// ---------------------------------------------------------------------------
+constexpr int kLeafRows = 16;   // rows per block (4 per wave)
+
+struct LeafArgs {
+  const double* M;        // X (first pass) or XT (second pass), [leaves][c][c]
+  const void* coef_in;    // first pass: coefficient image to gather from
+  double* y;              // [3][c]: first pass output, second pass input
+  void* coef_out;         // second pass: coefficient image to scatter into
+  int n, tiles, c, TS;
+  int py[3], px[3];
+};
+
+template <typename T, bool SECOND>
+__global__ __launch_bounds__(256) void k_leaf(LeafArgs a) {
+  extern __shared__ double vin[];
+  const int lf = blockIdx.y;
+  const int py = a.py[lf], px = a.px[lf];
+  const double* __restrict__ Mb = a.M + (size_t)(py * a.TS + px) * a.c * a.c;
+  for (int k = threadIdx.x; k < a.c; k += 256) {
+    if constexpr (!SECOND) {
+      const int ky = k / a.tiles, kx = k - ky * a.tiles;
+      vin[k] = (double)((const T*)a.coef_in)[((size_t)ky * a.TS + py) * a.n +
+                                               (size_t)kx * a.TS + px];
+    } else {
+      vin[k] = a.y[(size_t)lf * a.c + k];
+    }
+  }
+  __syncthreads();
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  for (int rr = 0; rr < kLeafRows / 4; ++rr) {
+    const int i = blockIdx.x * kLeafRows + wave * (kLeafRows / 4) + rr;
+    if (i >= a.c) break;   // uniform per wave
+    const double* __restrict__ row = Mb + (size_t)i * a.c;
+    // X is lower triangular (k <= i), XT upper (k >= i)
+    const int k0 = SECOND ? i : 0, k1 = SECOND ? a.c : i + 1;
+    double s = 0.0;
+    for (int k = k0 + lane; k < k1; k += 64) s = fma(row[k], vin[k], s);
+    s = wave_sum(s);
+    if (lane == 0) {
+      if constexpr (!SECOND) {
+        a.y[(size_t)lf * a.c + i] = s;
+      } else {
+        const int iy = i / a.tiles, ix = i - iy * a.tiles;
+        ((T*)a.coef_out)[((size_t)iy * a.TS + py) * a.n + (size_t)ix * a.TS + px] = (T)s;
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Set-up kernels (float64)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double walsh_sign(int qy, int qx, int py, int px) {
+  return ((__popc(qy & py) + __popc(qx & px)) & 1) ? -1.0 : 1.0;
+}
+
+// The basis image of packet (py, px) on tile (ty, tx) (set) or zeros (clear),
+// written into both padded copies; one thread per tile pixel.
+__global__ void k_basis(double* P, double* TP, int ld, int TS, int ty, int tx, int py, int px,
+                        int set) {
+  const int qy = threadIdx.x / TS, qx = threadIdx.x - qy * TS;
+  const double v = set ? walsh_sign(qy, qx, py, px) / (double)TS : 0.0;
+  const size_t iy = (size_t)ty * TS + qy, ix = (size_t)tx * TS + qx;
+  P[iy * ld + kPad + ix] = v;
+  TP[ix * ld + kPad + iy] = v;
+}
+
+// row[j] = packet (py, px) coefficient of tile j of img; one thread per tile.
+__global__ __launch_bounds__(256) void k_galerkin_row(const double* __restrict__ img, int n,
+                                                      int tiles, int TS, int py, int px,
+                                                      double* __restrict__ row) {
+  const int j = blockIdx.x * 256 + threadIdx.x;
+  if (j >= tiles * tiles) return;
+  const int ty = j / tiles, tx = j - ty * tiles;
+  double s = 0.0;
+  for (int qy = 0; qy < TS; ++qy)
+    for (int qx = 0; qx < TS; ++qx)
+      s += walsh_sign(qy, qx, py, px) * img[((size_t)ty * TS + qy) * n + (size_t)tx * TS + qx];
+  row[j] = s / (double)TS;
+}
+
+// thr = kHybridDropRel * (largest diagonal entry of all blocks); one block.
+__global__ __launch_bounds__(256) void k_drop_threshold(const double* __restrict__ S, int c,
+                                                        int leaves, double* thr) {
+  __shared__ double sh[256];
+  double mx = 0.0;
+  for (long long t = threadIdx.x; t < (long long)c * leaves; t += 256) {
+    const long long l = t / c, i = t - l * c;
+    mx = fmax(mx, S[(l * c + i) * c + i]);
+  }
+  sh[threadIdx.x] = mx;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + o]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *thr = kHybridDropRel * sh[0];
+}
+
+// Step k of the right-looking Cholesky factorisation of every block (lower
+// triangles): the column L[i][k] = S[i][k] / sqrt(S[k][k]) and the trailing
+// update S[i][j] -= S[i][k] S[j][k] / S[k][k] (k < j <= i), unless the pivot
+// is at most thr (dropped: column k of L stays zero, nothing is eliminated).
+// Column k of S is only read in this step.
+__global__ void k_chol_step(double* __restrict__ S, double* __restrict__ Lf, int c, int k,
+                            const double* __restrict__ thr) {
+  const int j = k + blockIdx.x * 16 + threadIdx.x;
+  const int i = k + blockIdx.y * 16 + threadIdx.y;
+  if (i >= c || j > i) return;
+  const size_t off = (size_t)blockIdx.z * c * c;
+  const double piv = S[off + (size_t)k * c + k];
+  if (!(piv > *thr)) return;
+  const double sik = S[off + (size_t)i * c + k];
+  if (j == k) Lf[off + (size_t)i * c + k] = sik / sqrt(piv);
+  else S[off + (size_t)i * c + j] -= sik * S[off + (size_t)j * c + k] / piv;
+}
+
+// Row i of X = L^-1 for every block: X[i][j] = (delta_ij - sum_{j<=k<i}
+// L[i][k] X[k][j]) / L[i][i] for j <= i; a dropped unknown (L[i][i] = 0) has
+// a zero row, and a zero column follows.  X starts zero.
+__global__ __launch_bounds__(256) void k_trinv_row(const double* __restrict__ Lf,
+                                                   double* __restrict__ X, int c, int i) {
+  const int j = blockIdx.x * 256 + threadIdx.x;
+  if (j > i) return;
+  const size_t off = (size_t)blockIdx.y * c * c;
+  const double lii = Lf[off + (size_t)i * c + i];
+  if (lii == 0.0) return;
+  double s = i == j ? 1.0 : 0.0;
+  for (int k = j; k < i; ++k) s -= Lf[off + (size_t)i * c + k] * X[off + (size_t)k * c + j];
+  X[off + (size_t)i * c + j] = s / lii;
+}
+
+__global__ __launch_bounds__(256) void k_transpose_blocks(const double* __restrict__ X,
+                                                          double* __restrict__ XT, int c) {
+  const size_t off = (size_t)blockIdx.z * c * c;
+  const int k = blockIdx.x * 16 + threadIdx.x, i = blockIdx.y * 16 + threadIdx.y;
+  if (i < c && k < c) XT[off + (size_t)k * c + i] = X[off + (size_t)i * c + k];
+}
+
+__global__ __launch_bounds__(256) void k_count_dropped(const double* __restrict__ X, int c,
+                                                       int leaves, int* out) {
+  __shared__ int sh[256];
+  int cnt = 0;
+  for (long long t = threadIdx.x; t < (long long)c * leaves; t += 256) {
+    const long long l = t / c, i = t - l * c;
+    cnt += X[(l * c + i) * c + i] == 0.0;
+  }
+  sh[threadIdx.x] = cnt;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = sh[0];
+}
+
+// ---------------------------------------------------------------------------
+// Host side
+// ---------------------------------------------------------------------------
+void dalloc(void** p, size_t bytes) {
+  if (hipMalloc(p, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    fail(RECO_ENOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed");
+  }
+}
+
+template <typename T>
+void launch_wht(const WhtArgs& a, int TS, hipStream_t st) {
+  const dim3 grid((unsigned)((a.tiles * a.tiles + 255) / 256));
+  switch (TS) {
+    case 2: hipLaunchKernelGGL((k_tile_wht<T, 2>), grid, dim3(256), 0, st, a); break;
+    case 4: hipLaunchKernelGGL((k_tile_wht<T, 4>), grid, dim3(256), 0, st, a); break;
+    default: hipLaunchKernelGGL((k_tile_wht<T, 8>), grid, dim3(256), 0, st, a); break;
+  }
+  HIP_CHECK(hipGetLastError());
+}
+
+WhtArgs wht_args(const Geometry& g, int tiles) {
+  WhtArgs a{};
+  a.n = g.n;
+  a.tiles = tiles;
+  a.src_ld = a.dst_ld = g.n;
+  return a;
+}
+
+// Cycle state of one apply.
+template <typename T>
+struct Cycle {
+  const Geometry& g;
+  const HybridFactors& f;
+  HybridScratch& s;
+  hipStream_t st;
+
+  void leaves(const void* in, const int (&py)[3], const int (&px)[3], int count) {
+    LeafArgs la{};
+    la.M = f.X;
+    la.coef_in = in;
+    la.y = s.y;
+    la.coef_out = s.coefE;
+    la.n = g.n;
+    la.tiles = f.tiles;
+    la.c = f.c;
+    la.TS = f.TS;
+    for (int i = 0; i < 3; ++i) {
+      la.py[i] = py[i];
+      la.px[i] = px[i];
+    }
+    const dim3 grid((unsigned)((f.c + kLeafRows - 1) / kLeafRows), (unsigned)count);
+    const size_t lds = sizeof(double) * f.c;
+    hipLaunchKernelGGL((k_leaf<T, false>), grid, dim3(256), lds, st, la);
+    la.M = f.XT;
+    hipLaunchKernelGGL((k_leaf<T, true>), grid, dim3(256), lds, st, la);
+    HIP_CHECK(hipGetLastError());
+  }
+
+  // r' = in - A_P e_LL on the positions of P's LH, HL and HH children, into
+  // coefR[l + 1]; e_LL is the correction on P's LL child's positions.
+  void residual_update(int l, int cy, int cx, const void* in) {
+    WhtArgs a = wht_args(g, f.tiles);
+    a.src = s.coefE;
+    a.in_depth = l + 1;
+    a.in_cy = cy;
+    a.in_cx = cx;
+    a.dst = s.P;
+    a.dstT = s.TP;
+    a.dst_ld = g.ld;
+    a.dst_off = kPad;
+    launch_wht<T>(a, f.TS, st);
+    FwdArgs fa{};
+    fa.imgP = s.P;
+    fa.imgTP = s.TP;
+    fa.out = s.sino;
+    launch_forward(g, FWD_PLAIN, fa, st);
+    BwdArgs ba{};
+    ba.sino = s.sino;
+    ba.out = s.img;
+    ba.x = s.P;
+    ba.x_ld = g.ld;
+    ba.x_off = kPad;
+    ba.sa = 1.0;
+    ba.sx = f.lambda;
+    launch_backward(g, BWD_AXPY, ba, st);
+    WhtArgs b = wht_args(g, f.tiles);
+    b.src = s.img;
+    b.dst = s.coefR[l + 1];
+    b.base = in;
+    b.sub = 1;
+    b.out_depth = l;
+    b.out_cy = cy;
+    b.out_cx = cx;
+    launch_wht<T>(b, f.TS, st);
+  }
+
+  void run(int l, int cy, int cx, const void* in) {
+    if (l == f.L) {
+      const int py[3] = {cy, 0, 0}, px[3] = {cx, 0, 0};
+      leaves(in, py, px, 1);
+      return;
+    }
+    const int hb = 1 << l;
+    run(l + 1, cy, cx, in);   // LL
+    residual_update(l, cy, cx, in);
+    const void* r2 = s.coefR[l + 1];
+    // LH (high along x), HL (high along y), HH
+    const int hy[3] = {cy, cy | hb, cy | hb}, hx[3] = {cx | hb, cx, cx | hb};
+    if (l + 1 == f.L) {
+      leaves(r2, hy, hx, 3);
+    } else {
+      for (int i = 0; i < 3; ++i) run(l + 1, hy[i], hx[i], r2);
+    }
+  }
+};
+
+template <typename T>
+void apply_impl(const Geometry& g, const HybridFactors& f, HybridScratch& s, const void* r,
+                void* outP, void* outTP, void* outPlain, hipStream_t st) {
+  WhtArgs a = wht_args(g, f.tiles);
+  a.src = r;
+  a.dst = s.coefR[0];
+  launch_wht<T>(a, f.TS, st);
+  Cycle<T> cyc{g, f, s, st};
+  cyc.run(0, 0, 0, s.coefR[0]);
+  if (outP) {
+    WhtArgs b = wht_args(g, f.tiles);
+    b.src = s.coefE;
+    b.dst = outP;
+    b.dstT = outTP;
+    b.dst_ld = g.ld;
+    b.dst_off = kPad;
+    launch_wht<T>(b, f.TS, st);
+  }
+  if (outPlain) {
+    WhtArgs b = wht_args(g, f.tiles);
+    b.src = s.coefE;
+    b.dst = outPlain;
+    launch_wht<T>(b, f.TS, st);
+  }
+}
+
+std::unique_ptr<HybridFactors> build_factors(Geometry& g, double lambda, hipStream_t st) {
+  auto f = std::make_unique<HybridFactors>();
+  f->L = g.L;
+  f->TS = 1 << g.L;
+  f->tiles = g.n >> g.L;
+  f->c = f->tiles * f->tiles;
+  f->leaves = f->TS * f->TS;
+  f->lambda = lambda;
+  const int c = f->c, TS = f->TS;
+  const size_t blk = (size_t)f->leaves * c * c;
+  // the Galerkin applies run on a float64 copy of the geometry (no WMG levels)
+  std::unique_ptr<Geometry> twin;
+  Geometry* g64 = &g;
+  if (!g.f64) {
+    reco_geometry_desc d = g.desc;
+    d.dtype = RECO_F64;
+    d.wmg_levels = 1;
+    twin.reset(create_geometry(d, st));
+    g64 = twin.get();
+  }
+  double *S = nullptr, *Lf = nullptr, *P = nullptr, *TP = nullptr, *sino = nullptr,
+         *img = nullptr, *thr = nullptr;
+  int* cnt = nullptr;
+  auto release = [&]() {
+    for (void* p : {(void*)S, (void*)Lf, (void*)P, (void*)TP, (void*)sino, (void*)img,
+                    (void*)thr, (void*)cnt})
+      if (p) (void)hipFree(p);
+  };
+  try {
+    dalloc((void**)&S, sizeof(double) * blk);
+    dalloc((void**)&Lf, sizeof(double) * blk);
+    dalloc((void**)&P, sizeof(double) * g64->padded_elems());
+    dalloc((void**)&TP, sizeof(double) * g64->padded_elems());
+    dalloc((void**)&sino, sizeof(double) * g64->M());
+    dalloc((void**)&img, sizeof(double) * g64->N());
+    dalloc((void**)&thr, sizeof(double));
+    dalloc((void**)&cnt, sizeof(int));
+    launch_fill(Lf, blk, true, 0.0, st);
+    launch_fill(P, g64->padded_elems(), true, 0.0, st);
+    launch_fill(TP, g64->padded_elems(), true, 0.0, st);
+    // Galerkin blocks: row i of block p = packet-p coefficients of K v_i
+    const unsigned rgrid = (unsigned)((c + 255) / 256);
+    for (int py = 0; py < TS; ++py) {
+      for (int px = 0; px < TS; ++px) {
+        double* Sp = S + (size_t)(py * TS + px) * c * c;
+        for (int i = 0; i < c; ++i) {
+          const int ty = i / f->tiles, tx = i - ty * f->tiles;
+          hipLaunchKernelGGL(k_basis, dim3(1), dim3(TS * TS), 0, st, P, TP, g64->ld, TS, ty, tx,
+                             py, px, 1);
+          FwdArgs fa{};
+          fa.imgP = P;
+          fa.imgTP = TP;
+          fa.out = sino;
+          launch_forward(*g64, FWD_PLAIN, fa, st);
+          BwdArgs ba{};
+          ba.sino = sino;
+          ba.out = img;
+          ba.x = P;
+          ba.x_ld = g64->ld;
+          ba.x_off = kPad;
+          ba.sa = 1.0;
+          ba.sx = lambda;
+          launch_backward(*g64, BWD_AXPY, ba, st);
+          hipLaunchKernelGGL(k_galerkin_row, dim3(rgrid), dim3(256), 0, st, (const double*)img,
+                             g64->n, f->tiles, TS, py, px, Sp + (size_t)i * c);
+          hipLaunchKernelGGL(k_basis, dim3(1), dim3(TS * TS), 0, st, P, TP, g64->ld, TS, ty, tx,
+                             py, px, 0);
+        }
+        HIP_CHECK(hipGetLastError());
+      }
+    }
+    hipLaunchKernelGGL(k_drop_threshold, dim3(1), dim3(256), 0, st, (const double*)S, c,
+                       f->leaves, thr);
+    for (int k = 0; k < c; ++k) {
+      const unsigned side = (unsigned)((c - k + 15) / 16);
+      hipLaunchKernelGGL(k_chol_step, dim3(side, side, f->leaves), dim3(16, 16), 0, st, S, Lf, c,
+                         k, (const double*)thr);
+    }
+    HIP_CHECK(hipGetLastError());
+    // X = L^-1 into S's storage, then X^T into L's
+    double* X = S;
+    launch_fill(X, blk, true, 0.0, st);
+    for (int i = 0; i < c; ++i)
+      hipLaunchKernelGGL(k_trinv_row, dim3((unsigned)((i + 256) / 256), f->leaves), dim3(256), 0,
+                         st, (const double*)Lf, X, c, i);
+    HIP_CHECK(hipGetLastError());
+    double* XT = Lf;
+    const unsigned side = (unsigned)((c + 15) / 16);
+    hipLaunchKernelGGL(k_transpose_blocks, dim3(side, side, f->leaves), dim3(16, 16), 0, st,
+                       (const double*)X, XT, c);
+    hipLaunchKernelGGL(k_count_dropped, dim3(1), dim3(256), 0, st, (const double*)X, c,
+                       f->leaves, cnt);
+    HIP_CHECK(hipGetLastError());
+    int dropped = 0;
+    HIP_CHECK(hipMemcpyAsync(&dropped, cnt, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIP_CHECK(hipStreamSynchronize(st));
+    f->dropped = dropped;
+    f->X = X;
+    f->XT = XT;
+    S = Lf = nullptr;
+    release();
+  } catch (...) {
+    (void)hipStreamSynchronize(st);
+    release();
+    throw;
+  }
+  return f;
+}
+
+}  // namespace
+
+HybridFactors::~HybridFactors() {
+  if (X) (void)hipFree(X);
+  if (XT) (void)hipFree(XT);
+}
+
+HybridScratch::~HybridScratch() {
+  for (void* p : coefR)
+    if (p) (void)hipFree(p);
+  for (void* p : {coefE, img, P, TP, sino, (void*)y})
+    if (p) (void)hipFree(p);
+}
+
+void validate_hybrid(const Geometry& g) {
+  if (g.L < 1 || g.L > kHybridMaxLevels)
+    fail(RECO_EINVAL, "the hybrid cycle needs 2 to 4 WMG levels (wmg_levels)");
+  const size_t tiles = (size_t)g.n >> g.L, c = tiles * tiles;
+  if (c > 4096)
+    fail(RECO_EINVAL, "the hybrid cycle's coarsest problems are limited to 4096 unknowns "
+                      "((n / 2^(wmg_levels - 1))^2)");
+  const size_t bytes = 2 * sizeof(double) * ((size_t)1 << (2 * g.L)) * c * c;
+  if (bytes > kHybridMaxFactorBytes)
+    fail(RECO_EINVAL, "the hybrid cycle's coarsest factors would need " + std::to_string(bytes) +
+                          " bytes (limit " + std::to_string(kHybridMaxFactorBytes) + ")");
+}
+
+const HybridFactors& ensure_hybrid(Geometry& g, double lambda, hipStream_t st) {
+  validate_hybrid(g);
+  std::lock_guard<std::mutex> lk(g.hyb_mu);
+  auto it = g.hyb.find(lambda);
+  if (it != g.hyb.end()) return *it->second;
+  auto f = build_factors(g, lambda, st);
+  const HybridFactors& ref = *f;
+  g.hyb.emplace(lambda, std::move(f));
+  return ref;
+}
+
+HybridScratch& hybrid_scratch(const Geometry& g, Workspace& w, hipStream_t st) {
+  if (w.hyb) return *w.hyb;
+  std::unique_ptr<HybridScratch> s(new HybridScratch());
+  const size_t es = g.esize();
+  for (int l = 0; l <= g.L; ++l) dalloc(&s->coefR[l], es * g.N());
+  dalloc(&s->coefE, es * g.N());
+  dalloc(&s->img, es * g.N());
+  dalloc(&s->P, es * g.padded_elems());
+  dalloc(&s->TP, es * g.padded_elems());
+  dalloc(&s->sino, es * g.M());
+  const size_t tiles = (size_t)g.n >> g.L;
+  dalloc((void**)&s->y, sizeof(double) * 3 * tiles * tiles);
+  // zero padding columns of the padded pair; the transforms write interiors
+  launch_fill(s->P, g.padded_elems(), g.f64, 0.0, st);
+  launch_fill(s->TP, g.padded_elems(), g.f64, 0.0, st);
+  w.hyb = s.release();
+  return *w.hyb;
+}
+
+void hybrid_apply(const Geometry& g, const HybridFactors& f, HybridScratch& s, const void* r,
+                  void* outP, void* outTP, void* outPlain, hipStream_t st) {
+  if (g.f64) apply_impl<double>(g, f, s, r, outP, outTP, outPlain, st);
+  else apply_impl<float>(g, f, s, r, outP, outTP, outPlain, st);
+}
+
+}  // namespace reco

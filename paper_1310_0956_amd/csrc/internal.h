@@ -6,6 +6,7 @@
 
 #include <atomic>
 #include <cstdint>
+#include <map>
 #include <memory>
 #include <mutex>
 #include <string>
@@ -67,7 +68,8 @@ struct BwdAngle {
 // ---------------------------------------------------------------------------
 // Geometry
 // ---------------------------------------------------------------------------
-struct Workspace;  // solver buffers (solve.hip)
+struct Workspace;      // solver buffers (solve.hip)
+struct HybridFactors;  // coarsest factors of the hybrid wavelet cycle (hybrid.hip)
 
 // Zero columns on each side of the padded image copies read by the forward
 // projector (see project.hip).
@@ -120,6 +122,10 @@ struct Geometry {
 
   // pool of solver workspaces
   ReusePool<Workspace> ws_pool;
+
+  // hybrid wavelet cycle: coarsest factors per Tikhonov weight (built on first use)
+  std::mutex hyb_mu;
+  std::map<double, std::unique_ptr<HybridFactors>> hyb;
 
   size_t N() const { return (size_t)n * n; }
   size_t M() const { return (size_t)m * nb; }

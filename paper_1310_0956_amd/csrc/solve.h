@@ -5,6 +5,8 @@
 
 namespace reco {
 
+struct HybridScratch;
+
 // Per-solve device buffers, pooled per geometry.
 struct Workspace {
   void *r = nullptr, *q = nullptr;            // [M] residual, projected direction
@@ -28,6 +30,7 @@ struct Workspace {
   double* gm = nullptr;                       // GMRES / BiCGStab small dense data
   size_t gm_cap = 0;                          // doubles allocated in gm
   bool tainted = false;                       // last solve ended abnormally: never pooled
+  HybridScratch* hyb = nullptr;               // hybrid wavelet cycle buffers (first use)
   ~Workspace();
 };
 

@@ -10,6 +10,7 @@
 #include <exception>
 
 #include "device_common.h"
+#include "hybrid.h"
 #include "solve.h"
 #include "timing.h"
 
@@ -23,6 +24,7 @@ Workspace::~Workspace() {
   f(r); f(q); f(s); f(p); f(zP); f(zTP); f(xP); f(xTP); f(tmp); f(fvec);
   f(partial); f(counter); f(st); f(hist); f(V); f(gm);
   if (h_st) (void)hipHostFree(h_st);
+  delete hyb;
 }
 
 static void alloc(void** p, size_t bytes) {
@@ -143,7 +145,10 @@ void validate_opts(const reco_solve_opts& o, bool gmres) {
   if (!(o.tol > 0.0) && o.fixed_iters <= 0) fail(RECO_EINVAL, "tol must be > 0");
   if (o.max_iter < 1 && o.fixed_iters <= 0) fail(RECO_EINVAL, "max_iter must be >= 1");
   if (!(o.lambda >= 0.0)) fail(RECO_EINVAL, "lambda must be >= 0");
-  if (o.precond != RECO_PRECOND_NONE && o.precond != RECO_PRECOND_WMG)
+  if (o.precond == RECO_PRECOND_WMG_HYBRID && !gmres)
+    fail(RECO_EINVAL, "the hybrid wavelet cycle is not symmetric: use it with GMRES or BiCGStab");
+  if (o.precond != RECO_PRECOND_NONE && o.precond != RECO_PRECOND_WMG &&
+      o.precond != RECO_PRECOND_WMG_HYBRID)
     fail(RECO_EINVAL, "unknown preconditioner");
   if (gmres && (o.restart < 1 || o.restart > 64)) fail(RECO_EINVAL, "restart must be in [1, 64]");
   if (o.history_cap < 0) fail(RECO_EINVAL, "history_cap must be >= 0");
