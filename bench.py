@@ -63,6 +63,9 @@ def parse():
                          "CGLS and BiCGStab with Joseph's kernel)")
     ap.add_argument("--profile-only", action="store_true",
                     help="only run the timed steps (for rocprofv3)")
+    ap.add_argument("--profile-workload", choices=("ct512", "ct2048"), default="ct512",
+                    help="workload of --profile-only: the 512^2 headline or the 2048^2 "
+                         "reconstruction")
     return ap.parse_args()
 
 
@@ -91,17 +94,67 @@ def source_hash(files):
     return m.hexdigest()[:16]
 
 
-def traffic_for(family):
+def traffic_for(family, workload="ct512"):
     """Calibrated HBM bytes per launch of a kernel family from the committed
-    rocprofv3 counter summary, if it was taken on the current kernel sources
-    (else None)."""
-    p = os.path.join(ROOT, "profiles", "traffic_ct512.json")
+    rocprofv3 counter summary of a workload, if it was taken on the current
+    kernel sources (else None)."""
+    p = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
     if not os.path.exists(p):
         return None
     ent = json.load(open(p)).get(family)
     if not ent or ent.get("source_sha256_16") != source_hash(ent["source_files"]):
         return None
     return ent.get("bytes_per_launch")
+
+
+def host_info():
+    """CPU model, logical CPU count and RAM of the host the oracle runs on."""
+    model, mem_gib = None, None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+        for line in open("/proc/meminfo"):
+            if line.startswith("MemTotal"):
+                mem_gib = round(int(line.split()[1]) / 2 ** 20, 1)
+                break
+    except OSError:
+        pass
+    return {"cpu_model": model, "logical_cpus": os.cpu_count(), "ram_gib": mem_gib}
+
+
+def roofline_of(kt, working, nnz, workload):
+    """Roofline object of the dominant projector from per-family HIP-event
+    totals: algorithmic updates (nnz per launch that did work) over the summed
+    launch durations, against the VALU lane-operation peak; beside it the
+    calibrated HBM traffic per launch from the committed counter summary and
+    the bandwidth fraction it implies."""
+    gups = {k: nnz * working[k] / (kt[k][1] * 1e-3) / 1e9 for k in working if kt[k][1] > 0}
+    dom = "forward" if kt["forward"][1] >= kt["backward"][1] else "backward"
+    peak = PEAK_VALU_LANE_OPS / ALG_OPS_PER_UPDATE / 1e9
+    avg_working_ms = kt[dom][1] / working[dom]
+    traffic = traffic_for(dom, workload)
+    out = {
+        "bound": "alu",
+        "kernel": dom,
+        "achieved": round(gups[dom], 3),
+        "peak": round(peak, 3),
+        "unit": "Gupdate/s",
+        "frac": round(gups[dom] / peak, 4),
+        "traffic": traffic,
+        "avg_launch_ms": round(kt[dom][1] / kt[dom][0], 5),
+        "avg_working_launch_ms": round(avg_working_ms, 5),
+        "launches": kt[dom][0],
+        "working_launches": working[dom],
+        "updates_per_working_launch": nnz,
+        "alg_valu_ops_per_update": ALG_OPS_PER_UPDATE,
+    }
+    if traffic:
+        gbs = traffic / (avg_working_ms * 1e-3) / 1e9
+        out["hbm_GBs_from_traffic"] = round(gbs, 1)
+        out["hbm_frac"] = round(gbs / HBM_PEAK_GBS, 4)
+    return out, gups
 
 
 def cpu_baseline(args):
@@ -462,6 +515,7 @@ SEMICONV_GRIDS = {
     "bicgstab": [1, 2, 3, 5, 7, 10, 15, 20, 30, 50, 70, 100, 150, 200, 300],
     "wmg_bicgstab": [1, 2, 3, 4, 5, 6, 8, 10, 12, 14, 17, 20, 25, 30, 40, 60, 100],
     "wmg_cgls": [1, 2, 3, 4, 5, 6, 8, 10, 12, 14, 17, 20, 25, 30, 40, 60, 100],
+    "wmg_hybrid_bicgstab": [1, 2, 3, 4, 5, 6, 8, 10, 12, 14, 17, 20, 25, 30, 40, 60, 100],
 }
 
 
@@ -494,12 +548,27 @@ def semiconv_leg(reco, torch):
              "bicgstab_reg": lambda k: g.solve_bicgstab(bn, fixed_iters=k, lam=lam,
                                                         precond=reco.PRECOND_NONE),
              "wmg_bicgstab_reg": lambda k: g.solve_bicgstab(bn, fixed_iters=k, lam=lam),
-             "wmg_cgls_reg": lambda k: g.solve_cgls(bn, fixed_iters=k, lam=lam)}
+             "wmg_cgls_reg": lambda k: g.solve_cgls(bn, fixed_iters=k, lam=lam),
+             "wmg_hybrid_bicgstab": lambda k: g.solve_bicgstab(
+                 bn, fixed_iters=k, precond=reco.PRECOND_WMG_HYBRID),
+             "wmg_hybrid_bicgstab_reg": lambda k: g.solve_bicgstab(
+                 bn, fixed_iters=k, lam=lam, precond=reco.PRECOND_WMG_HYBRID)}
     out = {"workload": "160^2 image, 400 angles x 160 rays, 10 ellipses, 1% uniform noise, "
-                       "3-level WMG, float32; error of fixed-iteration solves; *_reg: Tikhonov "
+                       "3-level WMG, float32; error of fixed-iteration solves; wmg_*: the "
+                       "additive packet-diagonal cycle, wmg_hybrid_*: the hybrid cycle with "
+                       "exact coarsest solves; *_reg: Tikhonov "
                        f"lambda = 10 h^2 = {lam:.6g}"}
+    # the hybrid cycle's coarsest Cholesky factors are built on first use per
+    # lambda (float64, one Galerkin apply per unknown): timed here as set-up
+    setup = {}
+    for key, la in (("lambda_0", 0.0), ("lambda_reg", lam)):
+        t0 = time.perf_counter()
+        g.wmg_hybrid_apply(xe, lam=la)
+        torch.cuda.synchronize()
+        setup[key] = round((time.perf_counter() - t0) * 1e3, 1)
+    out["hybrid_factor_setup_ms"] = setup
     grids = dict(SEMICONV_GRIDS)
-    for name in ("bicgstab", "wmg_bicgstab", "wmg_cgls"):
+    for name in ("bicgstab", "wmg_bicgstab", "wmg_cgls", "wmg_hybrid_bicgstab"):
         grids[name + "_reg"] = SEMICONV_GRIDS[name]
     for name, ks in grids.items():
         errs, done = [], []
@@ -511,6 +580,16 @@ def semiconv_leg(reco, torch):
         out[name] = {"k_opt": ks[i], "err_min": round(errs[i], 5),
                      "curve": [[k, round(e, 5)] for k, e in zip(ks, errs)],
                      "iters_run": done}
+    # time per iteration at the error-minimising iteration count (the paper's
+    # Table 3 compares whole solves to k_opt)
+    for name in ("bicgstab", "wmg_bicgstab", "wmg_hybrid_bicgstab"):
+        k = out[name]["k_opt"]
+        solve[name](k)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        solve[name](k)
+        torch.cuda.synchronize()
+        out[name]["ms_at_k_opt"] = round((time.perf_counter() - t0) * 1e3, 3)
     return out
 
 
@@ -582,7 +661,8 @@ def ct2048_leg(reco, torch):
     at_ms = kt_alone["backward"][1] / kt_alone["backward"][0]
     fwd = nnz * it / (kt["forward"][1] * 1e-3) / 1e9
     bwd = nnz * (it + reps) / (kt["backward"][1] * 1e-3) / 1e9
-    return {
+    roof, _ = roofline_of(kt, {"forward": it, "backward": it + reps}, nnz, "ct2048")
+    return roof, {
         "workload": "ct2048: 2048x2048 image, 2048 angles x 2897 bins, 40-ellipse phantom, "
                     "0.5% noise, 5-level WMG-CGLS to rel-res 1e-3",
         "recons_per_s": round(1.0 / t, 4), "ms_per_recon": round(t * 1e3, 2),
@@ -604,6 +684,35 @@ def ct2048_leg(reco, torch):
     }
 
 
+def copy_calibration(torch):
+    """Calibration for the HBM byte counters: plain device copies of a known
+    size (read COPY_BYTES, write COPY_BYTES) in the same profiled process."""
+    src = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+
+
+def profile_ct2048(reco, torch, args):
+    """The 2048^2 reconstruction alone (for rocprofv3): geometry set-up, then
+    warm-up and timed WMG-CGLS solves of one resident sinogram, then the copy
+    calibration."""
+    g = reco.Geometry(2048, 2048, 2897, 5, reco.F32)
+    b = gpu_sinogram(torch, g, 40, 2000, 0.005)
+    x = g.new_image()
+    for _ in range(args.warmup):
+        g.solve_cgls(b, x=x, tol=1e-3)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    iters = [g.solve_cgls(b, x=x, tol=1e-3)[1]["iters"] for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    copy_calibration(torch)
+    print(json.dumps({"workload": "ct2048", "steps": args.steps, "iters": iters,
+                      "seconds": elapsed, "copy_bytes": COPY_BYTES}))
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -616,6 +725,9 @@ def main():
     import paper_1310_0956_amd as reco
 
     torch.cuda.set_device(0)
+    if args.profile_only and args.profile_workload == "ct2048":
+        profile_ct2048(reco, torch, args)
+        return
     w = WORKLOAD
     t0 = time.perf_counter()
     g = reco.Geometry(w["n"], w["m"], w["nb"], w["levels"], reco.F32)
@@ -644,13 +756,7 @@ def main():
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     if args.profile_only:
-        # Calibration for the HBM byte counters: plain device copies of a known
-        # size (read COPY_BYTES, write COPY_BYTES) in the same profiled process.
-        src = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device="cuda")
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            dst.copy_(src)
-        torch.cuda.synchronize()
+        copy_calibration(torch)
         print(json.dumps({"steps": args.steps, "seconds": elapsed, "copy_bytes": COPY_BYTES}))
         return
 
@@ -669,25 +775,9 @@ def main():
     # once; its (short) duration still counts in the totals below.
     working = {"forward": work_iters, "backward": work_iters + args.steps}
     avg_ms = {k: (ms / n if n else 0.0) for k, (n, ms) in kt.items()}
-    gups = {k: nnz * working[k] / (kt[k][1] * 1e-3) / 1e9 for k in working if kt[k][1] > 0}
-    dom = "forward" if kt["forward"][1] >= kt["backward"][1] else "backward"
-    peak = PEAK_VALU_LANE_OPS / ALG_OPS_PER_UPDATE / 1e9
+    roofline, gups = roofline_of(kt, working, nnz, "ct512")
     N, M = w["n"] ** 2, w["m"] * w["nb"]
     spmv_bytes = 8.0 * nnz + 4.0 * (N + M)
-    roofline = {
-        "bound": "alu",
-        "kernel": dom,
-        "achieved": round(gups[dom], 3),
-        "peak": round(peak, 3),
-        "unit": "Gupdate/s",
-        "frac": round(gups[dom] / peak, 4),
-        "traffic": traffic_for(dom),
-        "avg_launch_ms": round(avg_ms[dom], 5),
-        "launches": kt[dom][0],
-        "working_launches": working[dom],
-        "updates_per_working_launch": nnz,
-        "alg_valu_ops_per_update": ALG_OPS_PER_UPDATE,
-    }
     result = {
         "metric": "WMG-CGLS recons/s at rel-res 1e-3; A/AT Gupdates/s; p50/p99 latency",
         "value": round(args.steps / elapsed, 3),
@@ -741,7 +831,8 @@ def main():
     if args.serve > 0:
         result["serving"] = serve_leg(reco, torch, args)
     if not args.no_ct2048:
-        result["ct2048"] = ct2048_leg(reco, torch)
+        progress("2048^2 reconstruction")
+        result["roofline_ct2048"], result["ct2048"] = ct2048_leg(reco, torch)
     if not args.no_tiny64:
         gc.collect()
         torch.cuda.synchronize()
@@ -763,6 +854,7 @@ def main():
                       f"512^2 workload (scipy CSR matrix, single thread) to rel-res 1e-3 in "
                       f"{t_sum:.2f} s, {cpu_iters} iterations; matrix assembly and packet "
                       f"diagonal excluded as setup",
+            "host": host_info(),
             "matvec_ct512": matvec,
             "tiny64_oracle": cpu_config0(),
         }

@@ -321,7 +321,9 @@ template <typename T>
 constexpr int kGroups = sizeof(T) == 4 ? 4 : 2;
 
 template <typename T, int MODE>
-__device__ __forceinline__ void backward_body(const BwdK<T>& a, const BlockPos pos) {
+__device__ __forceinline__ void backward_body(const BwdK<T>& a, const BlockPos hw) {
+  // the tile of this block: neighbouring tiles on one XCD share sinogram windows in its L2
+  const BlockPos pos = xcd_tile(hw);
   constexpr int G = kGroups<T>;
   // Solver state read with vector loads (an opaque zero index keeps them off
   // the scalar path: scalar loads share one out-of-order counter with LDS, so

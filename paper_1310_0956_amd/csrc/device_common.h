@@ -353,14 +353,41 @@ __device__ __forceinline__ void set_priority(int p) {
 }
 
 // Position of a block within its problem's grid.
+// Block coordinates (x, y) in a gx x gy grid and the block's linear dispatch
+// index `lin` (its slot in reductions; the highest one is dispatched last).
 struct BlockPos {
-  int x, y, gx, gy;
-  __device__ __forceinline__ int id() const { return y * gx + x; }
+  int x, y, gx, gy, lin;
+  __device__ __forceinline__ int id() const { return lin; }
   __device__ __forceinline__ int count() const { return gx * gy; }
 };
 
 __device__ __forceinline__ BlockPos grid_pos() {
-  return BlockPos{(int)blockIdx.x, (int)blockIdx.y, (int)gridDim.x, (int)gridDim.y};
+  return BlockPos{(int)blockIdx.x, (int)blockIdx.y, (int)gridDim.x, (int)gridDim.y,
+                  (int)(blockIdx.y * gridDim.x + blockIdx.x)};
+}
+
+// XCD-aware tile order.  Blocks are dealt to the eight XCDs round-robin by
+// dispatch index, so the blocks with lin % 8 == x share XCD x's L2.  XCD x is
+// given the x-th contiguous run of tiles in an order of 8-tile-wide column
+// bands (row-major within a band), so the tiles resident together on one XCD
+// are neighbours along both axes and read overlapping data through its L2.
+// A bijection of the grid; `lin` is kept.
+__device__ __forceinline__ BlockPos xcd_tile(const BlockPos b) {
+  constexpr int kBand = 8;
+  const int cnt = b.gx * b.gy, q = cnt >> 3, r = cnt & 7, xcd = b.lin & 7, j = b.lin >> 3;
+  const int t = xcd * q + min(xcd, r) + j;   // position in the band order
+  const int full = b.gx / kBand, span = kBand * b.gy;
+  int tx, ty;
+  if (t < full * span) {
+    const int band = t / span, rem = t - band * span;
+    ty = rem / kBand;
+    tx = band * kBand + (rem - ty * kBand);
+  } else {
+    const int rem = t - full * span, w = b.gx - full * kBand;
+    ty = rem / w;
+    tx = full * kBand + (rem - ty * w);
+  }
+  return BlockPos{tx, ty, b.gx, b.gy, b.lin};
 }
 
 // Problem owning flat block b in a batched launch: the last r with start[r] <= b.
@@ -378,7 +405,7 @@ __device__ __forceinline__ BlockPos batch_pos(const int* __restrict__ start,
                                               const int* __restrict__ gx, int r) {
   const int lb = (int)blockIdx.x - start[r];
   const int w = gx[r];
-  return BlockPos{lb % w, lb / w, w, (start[r + 1] - start[r]) / w};
+  return BlockPos{lb % w, lb / w, w, (start[r + 1] - start[r]) / w, lb};
 }
 
 }  // namespace reco

@@ -602,9 +602,13 @@ void build_forward_windows(Geometry& g, hipStream_t st) {
   HIP_CHECK(hipGetLastError());
   // Grid order: blocks walk from 1 to n rows depending on how far their bins
   // are from the detector centre.  Sorted by rows (most first) and dealt out
-  // in rounds of one block per CU, alternating direction, every run of
-  // consecutive grid positions of one CU count holds a similar amount of
-  // work; blocks are dispatched in grid order.
+  // in rounds of one block per CU, every run of consecutive grid positions of
+  // one CU count holds a similar amount of work; blocks are dispatched in grid
+  // order.  Within a round, positions p with p % 8 == x run on XCD x (blocks
+  // are dealt to the eight XCDs round-robin): each XCD is given a contiguous
+  // run of the round's blocks ordered by bin block, then angle group, so the
+  // blocks one XCD holds stage overlapping image strips (the same bins at
+  // neighbouring angles) through its L2.
   std::vector<int2> rows(nblk);
   HIP_CHECK(hipMemcpyAsync(rows.data(), g.d_fwd_rows, sizeof(int2) * nblk, hipMemcpyDeviceToHost,
                            st));
@@ -618,12 +622,18 @@ void build_forward_windows(Geometry& g, hipStream_t st) {
   HIP_CHECK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, g.device));
   const size_t P = (size_t)std::max(cus, 1);
   std::vector<int> order(nblk);
-  for (size_t r = 0; r < nblk; ++r) {
-    const size_t round = r / P, c = r % P;
-    const size_t base = round * P;
+  constexpr size_t kXcds = 8;
+  for (size_t base = 0; base < nblk; base += P) {
     const size_t width = std::min(P, nblk - base);
-    const size_t pos = base + ((round & 1) ? width - 1 - std::min(c, width - 1) : c);
-    order[pos] = byrows[r];
+    std::vector<int> round(byrows.begin() + base, byrows.begin() + base + width);
+    // block lb = angle group * nbx + bin block: order by bin block, then group
+    std::sort(round.begin(), round.end(), [&](int a, int b) {
+      const int ba = a % nbx, bb = b % nbx;
+      return ba != bb ? ba < bb : a < b;
+    });
+    size_t i = 0;
+    for (size_t x = 0; x < kXcds && x < width; ++x)
+      for (size_t p = x; p < width; p += kXcds) order[base + p] = round[i++];
   }
   HIP_CHECK(hipMemcpyAsync(g.d_fwd_order, order.data(), sizeof(int) * nblk, hipMemcpyHostToDevice,
                            st));
