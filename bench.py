@@ -46,7 +46,7 @@ def parse():
                     help="approximate CPU time spent on oracle reconstructions")
     ap.add_argument("--batch", type=int, default=256,
                     help="reconstructions in the batched leg (0: skip)")
-    ap.add_argument("--serve", type=int, default=120,
+    ap.add_argument("--serve", type=int, default=400,
                     help="requests in the serving leg (0: skip)")
     ap.add_argument("--serve-fracs", default="0.5,0.7,0.9",
                     help="arrival rates as fractions of the one-at-a-time saturation throughput")
@@ -234,12 +234,15 @@ def cpu_config0():
     b = W @ x
     d = wmg.packet_diagonal_by_angles(OG(n, m, nb), L)
     blocks = wmg.galerkin_blocks(W, n, L)
+    hybrid = wmg.HybridCycle(W, n, L)
     runs = [("sirt", lambda: solvers.sirt(W, b, fixed_iters=50)),
             ("cgls", lambda: solvers.pcgls(W, b, fixed_iters=50)),
             ("wmg_cgls_diag", lambda: solvers.pcgls(
                 W, b, fixed_iters=50, precond=lambda v: wmg.apply_additive_diag(v, d, L))),
             ("wmg_cgls_additive_exact", lambda: solvers.pcgls(
-                W, b, fixed_iters=50, precond=lambda v: wmg.apply_additive_exact(v, blocks, n, L)))]
+                W, b, fixed_iters=50, precond=lambda v: wmg.apply_additive_exact(v, blocks, n, L))),
+            ("wmg_hybrid_bicgstab", lambda: solvers.bicgstab_right(W, b, fixed_iters=50,
+                                                                   precond=hybrid))]
     out = {"workload": "tiny64 on the float64 oracle (the tiny64_f64 object's case), "
                        "50 iterations each"}
     for name, fn in runs:
@@ -595,7 +598,9 @@ def semiconv_leg(reco, torch):
 
 def tiny64_leg(reco, torch):
     """64^2, 90 angles x 64 bins, 10-ellipse noiseless phantom, float64:
-    50 iterations each of SIRT, CGLS and 2-level WMG-CGLS."""
+    50 iterations each of SIRT, CGLS and 2-level WMG-CGLS, and of BiCGStab
+    with the hybrid cycle and exact coarsest solves (its factors built before
+    the timing)."""
     import numpy as np
     import inputs
     g = reco.Geometry(64, 90, 64, 2, reco.F64)
@@ -608,7 +613,9 @@ def tiny64_leg(reco, torch):
     for name, fn in [("sirt", lambda: g.solve_sirt(b, x=xs, fixed_iters=50)),
                      ("cgls", lambda: g.solve_cgls(b, x=xs, fixed_iters=50,
                                                    precond=reco.PRECOND_NONE)),
-                     ("wmg_cgls", lambda: g.solve_cgls(b, x=xs, fixed_iters=50))]:
+                     ("wmg_cgls", lambda: g.solve_cgls(b, x=xs, fixed_iters=50)),
+                     ("wmg_hybrid_bicgstab", lambda: g.solve_bicgstab(
+                         b, x=xs, fixed_iters=50, precond=reco.PRECOND_WMG_HYBRID))]:
         fn()
         torch.cuda.synchronize()
         ts = []
