@@ -65,7 +65,8 @@ template <typename T>
 struct Meta {
   T base;   // bin coordinate of the tile centre minus the window start
   T c, s;   // direction cosines
-  T B, C0, C1, Wm;  // weight: w0 = clamp(C0 - f B), w1 = clamp(C1 + f B), in [0, Wm]
+  T B, C0, C1, Wm;  // weights Wm w0, Wm w1 with w0 = clamp(C0 - f B), w1 = clamp(C1 + f B)
+                    // in [0, 1]; Wm multiplies the staged window values
   int jw;   // first bin of the window
 };
 
@@ -135,11 +136,14 @@ __device__ __forceinline__ void fill_meta(Meta<T>* __restrict__ ring, const Raw<
   }
 }
 
-__device__ __forceinline__ float clampw(float v, float hi) { return __builtin_amdgcn_fmed3f(v, 0.0f, hi); }
-__device__ __forceinline__ double clampw(double v, double hi) { return fmin(fmax(v, 0.0), hi); }
+// The unit clamp, which the compiler folds into the producing FMA's output
+// clamp modifier.
+__device__ __forceinline__ float clamp01(float v) { return __builtin_amdgcn_fmed3f(v, 0.0f, 1.0f); }
+__device__ __forceinline__ double clamp01(double v) { return fmin(fmax(v, 0.0), 1.0); }
 
 // One pixel, one angle: the two candidate bins floor(J), floor(J)+1 of the
-// window, accumulated into acc.
+// window (values already multiplied by the angle's plateau Wm), accumulated
+// into acc.
 template <typename T>
 __device__ __forceinline__ T pixel_term(T J, const T* __restrict__ w, const Meta<T>& M, T acc) {
   const int j0 = (int)J;   // J > 0 inside the window: truncation is floor
@@ -147,8 +151,8 @@ __device__ __forceinline__ T pixel_term(T J, const T* __restrict__ w, const Meta
   if constexpr (sizeof(T) == 4) f = __builtin_amdgcn_fractf(J);
   else f = J - floor(J);
   const T r0 = w[j0], r1 = w[j0 + 1];
-  const T w0 = clampw(fma(f, -M.B, M.C0), M.Wm);
-  const T w1 = clampw(fma(f, M.B, M.C1), M.Wm);
+  const T w0 = clamp01(fma(f, -M.B, M.C0));
+  const T w1 = clamp01(fma(f, M.B, M.C1));
   return fma(w0, r0, fma(w1, r1, acc));
 }
 
@@ -172,6 +176,7 @@ template <typename T, int MODE>
 struct Stage {
   T r[kPerThread];
   T q[kCglsMode(MODE) ? kPerThread : 1];
+  T wa, wb;   // plateau Wm of the two rows (0 for rows past the last angle)
 };
 
 // Buffers of the window loads: the sinogram operand and, in the CGLS modes,
@@ -199,6 +204,8 @@ __device__ __forceinline__ void stage_load(Stage<T, MODE>& sg, const StageSrc& s
   const int ka = t / kRowLanes, kb = ka + kRowHalf;
   const int ja = mt[ka].jw + (t % kRowLanes), jb = mt[kb].jw + (t % kRowLanes);
   const bool rowa = ka < m - k0, rowb = kb < m - k0;
+  sg.wa = rowa ? mt[ka].Wm : T(0);
+  sg.wb = rowb ? mt[kb].Wm : T(0);
   // byte offsets of bins ja of angle k0 + ka and jb of angle k0 + kb (valid
   // bins lie below 2^31 bytes; rows past the last angle are never read at
   // these offsets)
@@ -242,16 +249,20 @@ __device__ __forceinline__ void stage_load(Stage<T, MODE>& sg, const StageSrc& s
 
 // Window values: the sinogram operand, in the CGLS modes the residual after
 // the current step, r - alpha q (the forward projector of the next iteration
-// stores the same value).
+// stores the same value), times the row's plateau Wm (one rounding).
 template <typename T, int MODE>
 __device__ __forceinline__ void stage_store(const Stage<T, MODE>& sg, T* __restrict__ w,
                                             double alpha, int t) {
   T* row = w + (t / kRowLanes) * kWin + (t % kRowLanes);
 #pragma unroll
   for (int i = 0; i < kPerThread; ++i) {
-    T v = sg.r[i];
-    if constexpr (kCglsMode(MODE)) v = (T)((double)sg.r[i] - alpha * (double)sg.q[i]);
     const int h = i / kPerRow, e = i % kPerRow;   // row (first or second), element
+    const T wm = h ? sg.wb : sg.wa;
+    T v;
+    if constexpr (kCglsMode(MODE))
+      v = (T)(((double)sg.r[i] - alpha * (double)sg.q[i]) * (double)wm);
+    else
+      v = sg.r[i] * wm;
     row[h * kRowHalf * kWin + kRowLanes * e] = v;
   }
 }

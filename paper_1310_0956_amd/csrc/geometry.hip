@@ -50,8 +50,9 @@ void build_angle_tables(Geometry& g) {
     f.inv = 1.0 / a;
     f.slope = -b / a;
     f.dP = std::llrint(f.slope * 4294967296.0);
-    f.B = v > 0 ? 1.0 / v : kAxisSlope;
-    f.C = 0.5 / u;
+    // the trapezoid's slope 1/v and offset 1/(2u), divided by Wmax = 1/u
+    f.B = (v > 0 ? 1.0 / v : kAxisSlope) * u;
+    f.C = 0.5;
     f.Wmax = 1.0 / u;
     f.Bf = (float)f.B;
     f.Cf = (float)f.C;
@@ -63,10 +64,12 @@ void build_angle_tables(Geometry& g) {
     const double vv = joseph ? uu : std::min(std::fabs(c), std::fabs(s));
     w.c = c;
     w.s = s;
-    w.B = vv > 0 ? 1.0 / (uu * vv) : kAxisSlope;
+    // the trapezoid's slope 1/(uu vv) and offsets, divided by Wmax = 1/uu
+    const double Bt = vv > 0 ? 1.0 / (uu * vv) : kAxisSlope;
     const double Cp = 0.5 / uu;
-    w.C0 = Cp + 0.5 * uu * w.B;
-    w.C1 = Cp + (0.5 * uu - 1.0) * w.B;
+    w.B = Bt * uu;
+    w.C0 = (Cp + 0.5 * uu * Bt) * uu;
+    w.C1 = (Cp + (0.5 * uu - 1.0) * Bt) * uu;
     w.Wmax = 1.0 / uu;
     w.cf = (float)c;
     w.sf = (float)s;
@@ -75,7 +78,7 @@ void build_angle_tables(Geometry& g) {
     w.C1f = (float)w.C1;
     w.Wmaxf = (float)w.Wmax;
     w.half_u_plus_v = 0.5 * (uu + vv);
-    w.inv_uv_d = w.B;
+    w.inv_uv_d = Bt;
     w.cc_d = vv > 0 ? (uu + vv) / (2.0 * uu * vv) : 0.5 * kAxisSlope + 0.5;
     w.inv_uv_f = (float)w.inv_uv_d;
     w.cc_f = (float)w.cc_d;

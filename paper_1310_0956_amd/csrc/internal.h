@@ -42,8 +42,9 @@ void check_hip(hipError_t e, const char* what, const char* file, int line);
 // image).  At major index r the ray crosses the minor axis at pixel-index
 // position P(j, r) = A0 + j*inv + r*slope; the two pixels floor(P) and
 // floor(P)+1 are the only ones with nonzero weight, and with f = P - floor(P)
-//   w0/h = clamp((1/2 - f) * B + C, 0, Wmax),   w1/h = Wmax - w0/h
-// (the weights of one row add up to the row's chord h/|a|).
+//   w0/h = Wmax clamp((1/2 - f) * B + C, 0, 1),   w1/h = Wmax - w0/h
+// (the weights of one row add up to the row's chord h Wmax = h/|a|; B and C
+// are the trapezoid's coefficients divided by its plateau Wmax).
 struct FwdAngle {
   double A0, inv, slope;
   long long dP;        // slope in 32.32 fixed point
@@ -56,7 +57,9 @@ struct FwdAngle {
 // Backprojector (pixel driven).  Pixel centre (X, Y) in pixel units from the
 // image centre projects to bin coordinate J = X c + Y s + (nb-1)/2; with
 // f = J - floor(J) the bins floor(J) and floor(J)+1 carry
-//   w0/h = clamp(C0 - f B, 0, Wmax),   w1/h = clamp(C1 + f B, 0, Wmax).
+//   w0/h = Wmax clamp(C0 - f B, 0, 1),   w1/h = Wmax clamp(C1 + f B, 0, 1)
+// (the trapezoid divided by its plateau height Wmax, so that the clamp is the
+// unit one).
 struct BwdAngle {
   double c, s, B, C0, C1, Wmax;
   float cf, sf, Bf, C0f, C1f, Wmaxf;

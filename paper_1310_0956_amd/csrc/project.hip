@@ -4,12 +4,13 @@
 // closer to the x axis, via a transposed image copy) the ray overlaps exactly
 // two candidate pixels, floor(P) and floor(P)+1, where P is the crossing
 // position in pixel units.  With f = P - floor(P) the weights are
-//   w0 = h clamp((1/2 - f) B + C, 0, 1/u),  w1 = h/u - w0,
-// u = |major direction cosine|, C = 1/(2u), from per-angle tables: for the
-// exact intersection lengths B = 1/v, v = |minor cosine| (the trapezoid of
-// the chord length against the ray offset), for Joseph's kernel B = 1/u
-// (w0 = h (1 - f)/u, the linear interpolation); the two weights of a row
-// always add up to the row's chord h/u.  Candidate columns are clamped to
+//   w0 = (h/u) clamp((1/2 - f) B + 1/2, 0, 1),  w1 = h/u - w0,
+// u = |major direction cosine|, from per-angle tables: for the exact
+// intersection lengths B = u/v, v = |minor cosine| (the trapezoid of the
+// chord length against the ray offset, divided by its plateau h/u), for
+// Joseph's kernel B = 1 (w0 = h (1 - f)/u, the linear interpolation); the two
+// weights of a row always add up to the row's chord h/u.  A ray sums the
+// unit-clamped weights and takes the factor h/u once at its end.  Candidate columns are clamped to
 // [-2, n]; the padded image copies carry kPad >= 2 zero columns on each side,
 // so a ray outside the image reads zeros.
 //
@@ -72,12 +73,13 @@ struct FwdK {
 
 __device__ __forceinline__ int iclamp(int v, int lo, int hi) { return min(max(v, lo), hi); }
 
-// Weight of the left candidate from the fraction (float and double forms).
-__device__ __forceinline__ float left_weight(float f, float B, float C, float Wm) {
-  return __builtin_amdgcn_fmed3f(fmaf(0.5f - f, B, C), 0.0f, Wm);
+// Weight of the left candidate from the fraction, divided by the plateau
+// (float and double forms).  The unit clamp folds into the FMA's output clamp.
+__device__ __forceinline__ float left_weight(float f, float B, float C) {
+  return __builtin_amdgcn_fmed3f(fmaf(0.5f - f, B, C), 0.0f, 1.0f);
 }
-__device__ __forceinline__ double left_weight(double f, double B, double C, double Wm) {
-  return fmin(fmax(fma(0.5 - f, B, C), 0.0), Wm);
+__device__ __forceinline__ double left_weight(double f, double B, double C) {
+  return fmin(fmax(fma(0.5 - f, B, C), 0.0), 1.0);
 }
 
 // Position walker along the rows of one ray.  col() is the column of the left
@@ -140,10 +142,11 @@ __device__ __forceinline__ T wM(const FwdAngle& a) {
 // clamped as an unsigned value to `width`, so a ray left or right of the
 // window (only rays outside the image can be) reads the zero guard columns
 // width and width + 1; rays inside the image stay in [0, width - 2].  The left
-// weight is clamp(lo * Bq + Cq, 0, Wm) with lo the 32-bit fraction of the
-// position, Bq = -B 2^-32 and Cq = C + B/2 (the trapezoid (1/2 - f) B + C).
+// weight (over the plateau) is clamp(lo * Bq + Cq, 0, 1) with lo the 32-bit
+// fraction of the position, Bq = -B 2^-32 and Cq = C + B/2 (the trapezoid
+// (1/2 - f) B + C).
 __device__ __forceinline__ void band_lds(const float* __restrict__ w, Walk<float>& wk, int rows,
-                                         unsigned width, float Bq, float Cq, float Wm,
+                                         unsigned width, float Bq, float Cq,
                                          float& acc0, float& acc1) {
   unsigned long long p = wk.p;
   const unsigned long long dp = wk.dp;
@@ -156,7 +159,7 @@ __device__ __forceinline__ void band_lds(const float* __restrict__ w, Walk<float
       const float* q = w + (r + u) * kStride + c;
       x0[u] = q[0];
       x1[u] = q[1];
-      w0[u] = __builtin_amdgcn_fmed3f(fmaf((float)(unsigned)p, Bq, Cq), 0.0f, Wm);
+      w0[u] = __builtin_amdgcn_fmed3f(fmaf((float)(unsigned)p, Bq, Cq), 0.0f, 1.0f);
       p += dp;
       asm volatile("" : "+v"(p));   // one position register: keep LLVM from cloning it per row
     }
@@ -170,7 +173,7 @@ __device__ __forceinline__ void band_lds(const float* __restrict__ w, Walk<float
     const unsigned c = min((unsigned)(p >> 32), width);
     const float* q = w + r * kStride + c;
     const float x0 = q[0], x1 = q[1];
-    acc0 = fmaf(__builtin_amdgcn_fmed3f(fmaf((float)(unsigned)p, Bq, Cq), 0.0f, Wm), x0 - x1, acc0);
+    acc0 = fmaf(__builtin_amdgcn_fmed3f(fmaf((float)(unsigned)p, Bq, Cq), 0.0f, 1.0f), x0 - x1, acc0);
     acc1 += x1;
     p += dp;
   }
@@ -180,13 +183,13 @@ __device__ __forceinline__ void band_lds(const float* __restrict__ w, Walk<float
 // Double path: the window-relative column is clamped into [lo_w, hi_w], the
 // window images of image columns -2 and n.
 __device__ __forceinline__ void band_lds(const double* __restrict__ w, Walk<double>& wk, int rows,
-                                         int lo_w, int hi_w, double B, double C, double Wm,
+                                         int lo_w, int hi_w, double B, double C,
                                          double& acc0, double& acc1) {
   for (int r = 0; r < rows; ++r) {
     const int c = iclamp(wk.col(), lo_w, hi_w);
     const double* q = w + r * kStride + c;
     const double x0 = q[0], x1 = q[1];
-    acc0 = fma(left_weight(wk.frac(), B, C, Wm), x0 - x1, acc0);
+    acc0 = fma(left_weight(wk.frac(), B, C), x0 - x1, acc0);
     acc1 += x1;
     wk.step();
   }
@@ -196,13 +199,13 @@ __device__ __forceinline__ void band_lds(const double* __restrict__ w, Walk<doub
 // the LDS window).  The walker's column is relative to image column c0.
 template <typename T>
 __device__ __forceinline__ void band_mem(__amdgpu_buffer_rsrc_t rs, int ld, int n, int r0, int rows,
-                                         int c0, Walk<T>& wk, T B, T C, T Wm, T& acc0, T& acc1) {
+                                         int c0, Walk<T>& wk, T B, T C, T& acc0, T& acc1) {
   for (int r = 0; r < rows; ++r) {
     const int c = iclamp(wk.col() + c0, -2, n) + kPad;
     const int soff = (r0 + r) * ld * (int)sizeof(T);
     const T x0 = load_elem(rs, (unsigned)c * sizeof(T), soff, T(0));
     const T x1 = load_elem(rs, (unsigned)(c + 1) * sizeof(T), soff, T(0));
-    acc0 = fma(left_weight(wk.frac(), B, C, Wm), x0 - x1, acc0);
+    acc0 = fma(left_weight(wk.frac(), B, C), x0 - x1, acc0);
     acc1 += x1;
     wk.step();
   }
@@ -413,12 +416,12 @@ __device__ __forceinline__ void forward_body(const FwdK<T>& a, const BlockPos bp
     const int width = wcur.c1 - wcur.c0 + 1;
     if (width <= kWinCols) {
       if constexpr (sizeof(T) == 4)
-        band_lds(win[cur], wk, rows, (unsigned)width, Bq, Cq, Wm, acc0, acc1);
+        band_lds(win[cur], wk, rows, (unsigned)width, Bq, Cq, acc0, acc1);
       else
-        band_lds(win[cur], wk, rows, max(-2 - wcur.c0, 0), min(n - wcur.c0, width - 2), B, C, Wm,
+        band_lds(win[cur], wk, rows, max(-2 - wcur.c0, 0), min(n - wcur.c0, width - 2), B, C,
                  acc0, acc1);
     } else {
-      band_mem<T>(rs, a.ld, n, rb, rows, wcur.c0, wk, B, C, Wm, acc0, acc1);
+      band_mem<T>(rs, a.ld, n, rb, rows, wcur.c0, wk, B, C, acc0, acc1);
     }
     if (next_lds) {
 #pragma unroll
@@ -429,7 +432,7 @@ __device__ __forceinline__ void forward_body(const FwdK<T>& a, const BlockPos bp
     __syncthreads();
   }
   set_priority(3);
-  const T result = (T)a.h * fma(Wm, acc1, acc0);
+  const T result = (T)a.h * (Wm * (acc0 + acc1));
   const size_t i = (size_t)k * nb + j;   // valid lanes only use it
   if constexpr (MODE == FWD_PLAIN) {
     if (valid) a.out[i] = result;
@@ -482,14 +485,14 @@ __global__ __launch_bounds__(256) void k_count(const FwdAngle* __restrict__ angs
     const int k = (int)(ray / nb), j = (int)(ray % nb);
     const FwdAngle ang = angs[k];
     const double P0 = fma((double)j, ang.inv, ang.A0);
-    const double eps = 1e-9 * ang.Wmax;
+    constexpr double eps = 1e-9;   // of the plateau
     for (int r = 0; r < n; ++r) {
       const double P = fma((double)r, ang.slope, P0);
       if (P < -2.0 || P > n + 1.0) continue;
       const double fl = floor(P);
       const int i0 = (int)fl;
-      const double w0 = fmin(fmax(fma(0.5 - (P - fl), ang.B, ang.C), 0.0), ang.Wmax);
-      const double w1 = ang.Wmax - w0;
+      const double w0 = fmin(fmax(fma(0.5 - (P - fl), ang.B, ang.C), 0.0), 1.0);
+      const double w1 = 1.0 - w0;
       cnt += (w0 > eps && i0 >= 0 && i0 < n) ? 1 : 0;
       cnt += (w1 > eps && i0 + 1 >= 0 && i0 + 1 < n) ? 1 : 0;
     }
