@@ -158,7 +158,7 @@ Geometry* create_geometry(const reco_geometry_desc& d, hipStream_t st) {
                            hipMemcpyHostToDevice, st));
   build_forward_windows(*g, st);
   HIP_CHECK(hipMalloc(&g->d_diag64, sizeof(double) * g->N()));
-  HIP_CHECK(hipMalloc(&g->d_diag, g->esize() * g->N()));
+  HIP_CHECK(hipMalloc(&g->d_diag, std::max(g->esize() * g->N(), diag_sum_bytes(g->n, g->L))));
   compute_packet_diagonal(*g, st);
   HIP_CHECK(hipStreamSynchronize(st));
   return g.release();

@@ -4,6 +4,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <atomic>
 #include <cstdint>
 #include <map>
@@ -116,7 +117,8 @@ struct Geometry {
 
   // packet diagonal (in-place tile layout, see wmg.hip), float64 always
   double* d_diag64 = nullptr;   // [n*n]
-  void* d_diag = nullptr;       // [n*n] in the geometry dtype (for the apply)
+  void* d_diag = nullptr;       // [n*n] in the geometry dtype (for the apply);
+                                // max(n*n*esize, diag_sum_bytes) bytes
 
   // SIRT weights (lazily built): R [M], C [N] in the geometry dtype
   std::mutex sirt_mu;
@@ -271,6 +273,9 @@ struct WmgArgs {
 void launch_wmg(const Geometry& g, WmgMode mode, const WmgArgs& a, hipStream_t st);
 int wmg_blocks(const Geometry& g);
 void compute_packet_diagonal(Geometry& g, hipStream_t st);
+// Bytes of the packet diagonal's running sums (held, during setup, in the
+// memory of the dtype copy of d, which is allocated at least this large).
+size_t diag_sum_bytes(int n, int L);
 
 // vector kernels (vec.hip)
 void launch_fill(void* p, size_t count, bool f64, double value, hipStream_t st);

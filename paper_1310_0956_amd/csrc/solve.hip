@@ -91,7 +91,8 @@ size_t geometry_bytes(const reco_geometry_desc& d) {
   const size_t bands = (size_t)(d.n + 15) / 16;
   const size_t blocks = groups * (size_t)((d.n_bins + 31) / 32);
   return (sizeof(FwdAngle) + sizeof(BwdAngle) + 8 * sizeof(int)) * (size_t)(d.n_angles + 8) +
-         blocks * ((bands + 1) * 8 + 4 + sizeof(FwdBlk)) + N * (8 + es) + 4096;
+         blocks * ((bands + 1) * 8 + 4 + sizeof(FwdBlk)) + N * 8 +
+         std::max(N * es, diag_sum_bytes(d.n, d.wmg_levels - 1)) + 4096;
 }
 
 bool return_workspace(Geometry& g, Workspace* w) {

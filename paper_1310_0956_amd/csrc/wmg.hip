@@ -242,23 +242,34 @@ __device__ __forceinline__ void y_stages(T (&w)[1 << L], const T (&sgn)[L > 0 ? 
 // summed per angle in the tile's precision and added to float64 sums, in a
 // fixed order (deterministic, no atomics).
 // The butterflies keep the low element as u + v and the high one as u - v, so
-// the coefficients land in the in-place layout of the apply.
-// One launch covers angles [k0, k1): the running float64 sums are kept in d64
-// between launches (first: start from zero), and the last launch scales them
-// and writes both copies.  The angle order, hence the result, does not depend
-// on how the angles are split over launches.
+// the coefficients land in the in-place layout of the apply (x frequency u at
+// tile column u, y frequency v at tile row v).
+//
+// Symmetries of the geometry cut the work by four.  Bins are centred on the
+// rotation centre, so the tile mirrored through the image centre sees, at
+// every angle, the mirrored weights of bin nb - 1 - j (its pixels rotated by
+// half a turn, which changes only the signs of the Walsh coefficients): equal
+// sums, so only the tiles t < ceil(tiles / 2) (row-major index) are computed.
+// With m even, angle k + m/2 is angle k turned by a quarter: its weights on
+// tile (tx, ty) are angle k's on tile (ty, N - 1 - tx) turned by a quarter, so
+// its coefficient (u, v) there is angle k's (v, u) up to sign; the angles
+// k < m/2 are summed and k_diag_assemble adds the turned tile's transposed
+// sums.
+// One launch covers angles [k0, k1): the running float64 sums S, compact per
+// computed tile ([tile][row][column]), are kept in memory between launches
+// (first: start from zero).  The angle order, hence the result, does not
+// depend on how the angles are split over launches.
 template <typename T, int L>
-__global__ __launch_bounds__(256) void k_packet_diag(const BwdAngle* __restrict__ ang, double* d64,
-                                                     T* dT, int n, int nb, double h, int k0,
-                                                     int k1, int first, int last) {
+__global__ __launch_bounds__(256) void k_packet_diag(const BwdAngle* __restrict__ ang, double* S,
+                                                     int n, int nb, int k0, int k1, int first,
+                                                     int nh) {
   constexpr int Tt = 1 << L;
   constexpr int TPW = 64 / Tt;   // tiles per wave
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int tiles_x = n / Tt;
-  const int ntiles = tiles_x * tiles_x;
   const int tile = (blockIdx.x * 4 + wv) * TPW + lane / Tt;
   const int y = lane & (Tt - 1);
-  const bool active = tile < ntiles;
+  const bool active = tile < nh;
   const int tyT = active ? tile / tiles_x : 0, txT = active ? tile % tiles_x : 0;
   const double hc = 0.5 * (n - 1), hb = 0.5 * (nb - 1);
   const double Xt = txT * Tt + 0.5 * (Tt - 1) - hc;   // tile centre, pixel units
@@ -267,10 +278,10 @@ __global__ __launch_bounds__(256) void k_packet_diag(const BwdAngle* __restrict_
   T sgn[L > 0 ? L : 1];   // y stage b: +1 keeps u + v (low lane), -1 gives u - v (high lane)
 #pragma unroll
   for (int b = 0; b < L; ++b) sgn[b] = ((y >> b) & 1) ? T(-1) : T(1);
+  double* const mine = S + ((size_t)tile * Tt + y) * Tt;   // this lane's tile row
   double acc[Tt];
 #pragma unroll
-  for (int x = 0; x < Tt; ++x)
-    acc[x] = (first || !active) ? 0.0 : d64[(size_t)(tyT * Tt + y) * n + txT * Tt + x];
+  for (int x = 0; x < Tt; ++x) acc[x] = (first || !active) ? 0.0 : mine[x];
 
   for (int k = k0; k < k1; ++k) {
     const BwdAngle A = ang[k];
@@ -319,42 +330,71 @@ __global__ __launch_bounds__(256) void k_packet_diag(const BwdAngle* __restrict_
     for (int x = 0; x < Tt; ++x) acc[x] += (double)part[x];
   }
   if (active) {
-    const double scale = h * h / (double)(1u << (2 * L));
-    const int iy = tyT * Tt + y;
 #pragma unroll
-    for (int x = 0; x < Tt; ++x) {
-      const int ix = txT * Tt + x;
-      if (last) {
-        const double v = acc[x] * scale;
-        d64[(size_t)iy * n + ix] = v;
-        dT[(size_t)iy * n + ix] = (T)v;
-      } else {
-        d64[(size_t)iy * n + ix] = acc[x];
-      }
-    }
+    for (int x = 0; x < Tt; ++x) mine[x] = acc[x];
   }
+}
+
+// d (float64, in-place layout) from the sums of the computed tiles: tile t's
+// own (or its mirror's) plus, with paired angles, the transposed sums of the
+// quarter-turned tile, times h^2 4^-L.
+template <int L>
+__global__ __launch_bounds__(256) void k_diag_assemble(const double* __restrict__ S,
+                                                       double* __restrict__ d64, int n, int pair,
+                                                       double scale) {
+  constexpr int Tt = 1 << L;
+  const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= (size_t)n * n) return;
+  const int iy = (int)(i / n), ix = (int)(i % n);
+  const int N = n >> L, nt = N * N, nh = (nt + 1) / 2;
+  const int tx = ix >> L, ty = iy >> L, u = ix & (Tt - 1), v = iy & (Tt - 1);
+  auto computed = [&](int t) { return t < nh ? t : nt - 1 - t; };
+  double sum = S[((size_t)computed(ty * N + tx) * Tt + v) * Tt + u];
+  if (pair) sum += S[((size_t)computed((N - 1 - tx) * N + ty) * Tt + u) * Tt + v];
+  d64[i] = sum * scale;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_diag_round(const double* __restrict__ d64,
+                                                    T* __restrict__ dT, size_t count) {
+  const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < count) dT[i] = (T)d64[i];
 }
 
 // The angles are split over launches of about a millisecond each: every block
 // of a launch stays resident for the whole launch, so kernels of other
-// streams (the solves of a server) get the CUs between launches.
+// streams (the solves of a server) get the CUs between launches.  The running
+// sums live in the memory of the dtype copy of d (diag_sum_bytes), which is
+// written last.
 template <typename T, int L>
 void diag_launch_L(Geometry& g, hipStream_t st) {
   const int ntiles = (g.n >> L) * (g.n >> L);
+  const int nh = (ntiles + 1) / 2;
+  const int pair = g.m % 2 == 0 ? 1 : 0;
+  const int mh = pair ? g.m / 2 : g.m;
+  double* S = (double*)g.d_diag;
   const int tiles_per_block = 4 * (64 >> L);
-  const int blocks = (ntiles + tiles_per_block - 1) / tiles_per_block;
+  const int blocks = (nh + tiles_per_block - 1) / tiles_per_block;
   // butterfly work of one angle: tiles x bins reaching a tile x 4^L * 2L;
   // about 1.5e13 of these per second (measured at 2048^2, 2^L = 16)
   const double Tt = (double)(1 << L);
-  const double per_angle = (double)ntiles * (1.2 * Tt + 3.0) * Tt * Tt * (2.0 * L + 1.0);
-  const int per_launch = (int)std::max(1.0, std::min((double)g.m, 1.5e10 / per_angle));
-  for (int k0 = 0; k0 < g.m; k0 += per_launch) {
-    const int k1 = std::min(g.m, k0 + per_launch);
+  const double per_angle = (double)nh * (1.2 * Tt + 3.0) * Tt * Tt * (2.0 * L + 1.0);
+  const int per_launch = (int)std::max(1.0, std::min((double)mh, 1.5e10 / per_angle));
+  for (int k0 = 0; k0 < mh; k0 += per_launch) {
+    const int k1 = std::min(mh, k0 + per_launch);
     TimedLaunch tl(TK_PACKET_DIAG, st);
-    hipLaunchKernelGGL((k_packet_diag<T, L>), dim3(blocks), dim3(256), 0, st, g.d_bwd, g.d_diag64,
-                       (T*)g.d_diag, g.n, g.nb, g.h, k0, k1, k0 == 0 ? 1 : 0, k1 == g.m ? 1 : 0);
+    hipLaunchKernelGGL((k_packet_diag<T, L>), dim3(blocks), dim3(256), 0, st, g.d_bwd, S, g.n,
+                       g.nb, k0, k1, k0 == 0 ? 1 : 0, nh);
     HIP_CHECK(hipGetLastError());
   }
+  const size_t N = (size_t)g.n * g.n;
+  const unsigned eblocks = (unsigned)((N + 255) / 256);
+  hipLaunchKernelGGL((k_diag_assemble<L>), dim3(eblocks), dim3(256), 0, st, S, g.d_diag64, g.n,
+                     pair, g.h * g.h / (double)(1u << (2 * L)));
+  HIP_CHECK(hipGetLastError());
+  hipLaunchKernelGGL((k_diag_round<T>), dim3(eblocks), dim3(256), 0, st, g.d_diag64, (T*)g.d_diag,
+                     N);
+  HIP_CHECK(hipGetLastError());
 }
 
 template <typename T>
@@ -412,6 +452,11 @@ void launch_wmg_batch(const DevTable& t, WmgMode mode, hipStream_t st) {
     default: fail(RECO_EINVAL, "unsupported batched WMG mode");
   }
   HIP_CHECK(hipGetLastError());
+}
+
+size_t diag_sum_bytes(int n, int L) {
+  const size_t N = (size_t)(n >> L);
+  return sizeof(double) * ((N * N + 1) / 2) * ((size_t)1 << (2 * L));
 }
 
 void compute_packet_diagonal(Geometry& g, hipStream_t st) {

@@ -40,6 +40,12 @@ CASES = [
     (128, 37, 182, 5, True),
     (64, 45, 91, 6, False),
     (64, 45, 91, 6, True),
+    # odd tile counts per side (the centre tile is its own mirror), even and odd m
+    (48, 30, 70, 5, False),
+    (48, 30, 70, 5, True),
+    (40, 21, 57, 4, False),
+    (40, 21, 57, 4, True),
+    (24, 12, 35, 4, True),
 ]
 TOL = {False: 1e-5, True: 1e-12}
 

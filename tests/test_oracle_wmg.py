@@ -1,6 +1,7 @@
 """Pins of the oracle WMG preconditioners.
 
-  * the packet diagonal equals diag(H_L W^T W H_L^T) from dense matrices (+ lam);
+  * the packet diagonal equals diag(H_L W^T W H_L^T) from dense matrices (+ lam),
+    and has the mirror and quarter-turn symmetries of the geometry;
   * additive-exact inverts K when K = H_L^T B H_L with B block diagonal over packets;
   * additive-diagonal inverts K when B is diagonal;
   * the hybrid cycle also inverts such K exactly (the packet subspaces are then
@@ -13,7 +14,7 @@ import scipy.linalg as sla
 
 from oracle import haar, wmg
 from oracle.geometry import Geometry
-from oracle.projector import system_matrix
+from oracle.projector import angle_block, system_matrix
 
 
 @pytest.mark.parametrize("n,m,nb,L,lam", [(8, 10, 12, 1, 0.0), (16, 12, 23, 2, 0.0),
@@ -28,6 +29,62 @@ def test_packet_diagonal_brute_force(n, m, nb, L, lam):
     assert np.allclose(d.ravel(), want, rtol=1e-13, atol=1e-15)
     d2 = wmg.packet_diagonal_by_angles(g, L, lam)
     assert np.allclose(d2, d, rtol=1e-13, atol=1e-15)
+
+
+def _quadrant_to_tile_local(dq, L):
+    """Packet diagonal from the quadrant layout (packet (pr, pc) in block
+    [pr cs, (pr + 1) cs) x [pc cs, (pc + 1) cs), cs = n / 2^L) to the tile-local
+    layout: tile (tx, ty) of 2^L x 2^L pixels holds its own coefficients, the
+    packet's row and column bits read least significant level first."""
+    n = dq.shape[0]
+    T = 1 << L
+    out = np.empty_like(dq)
+    for iy in range(n):
+        for ix in range(n):
+            ly, lx = iy & (T - 1), ix & (T - 1)
+            row, col = iy >> L, ix >> L
+            for lev in range(1, L + 1):
+                row += ((ly >> (lev - 1)) & 1) * (n >> lev)
+                col += ((lx >> (lev - 1)) & 1) * (n >> lev)
+            out[iy, ix] = dq[row, col]
+    return out
+
+
+@pytest.mark.parametrize("n,m,nb,L", [(16, 8, 23, 2), (12, 8, 17, 2), (12, 7, 17, 2),
+                                      (24, 12, 35, 3), (6, 4, 9, 0)])
+def test_packet_diagonal_symmetries(n, m, nb, L):
+    """The geometry's symmetries, on which the device computation of d rests:
+    with bins centred on the rotation centre, a tile and its mirror through the
+    image centre have equal sums at every angle, and (m even) angle k + m/2 is
+    angle k turned by a quarter, so on tile (tx, ty) it gives angle k's sums of
+    tile (ty, N - 1 - tx) with the packet row and column exchanged.  Summing the
+    angles k < m/2 (all angles for odd m) over the tiles t < ceil(N^2 / 2) and
+    assembling must give the full diagonal."""
+    g = Geometry(n, m, nb)
+    full = _quadrant_to_tile_local(wmg.packet_diagonal_by_angles(g, L), L)
+    pair = m % 2 == 0
+    mh = m // 2 if pair else m
+    half = _quadrant_to_tile_local(
+        wmg.packet_diagonal([angle_block(g, k) for k in range(mh)], n, L), L)
+    T, N = 1 << L, n >> L
+    nt = N * N
+    nh = (nt + 1) // 2
+
+    def tile(t):   # the computed tile standing for tile t, its sums
+        t = t if t < nh else nt - 1 - t
+        ty, tx = divmod(t, N)
+        return half[ty * T:(ty + 1) * T, tx * T:(tx + 1) * T]
+
+    got = np.empty_like(full)
+    for ty in range(N):
+        for tx in range(N):
+            blk = tile(ty * N + tx).copy()
+            if pair:
+                blk += tile((N - 1 - tx) * N + ty).T
+            got[ty * T:(ty + 1) * T, tx * T:(tx + 1) * T] = blk
+    assert np.allclose(got, full, rtol=1e-12, atol=1e-14 * full.max())
+    # the identity is not vacuous: the angles differ and tiles differ
+    assert not np.allclose(half, full - half, rtol=1e-3) or not pair
 
 
 def _block_diag_K(n, L, seed, diagonal=False):
