@@ -1,9 +1,9 @@
 // Backprojector s = W^T r (Section 2.1), pixel driven, no atomics.
 //
 // A block owns a 16 x 16 pixel tile; it holds several angle groups of two
-// waves (two pixels per thread), each looping over its share of the angle
-// chunks (32 angles each); their partial sums are added in group order at the
-// end (no atomics).  For each angle of a chunk the tile's
+// waves (two pixels per thread), each looping over its contiguous equal share
+// of the angles in chunks of 32; their partial sums are added in group order
+// at the end (no atomics).  For each angle of a chunk the tile's
 // detector footprint (at most 23 bins for a 16-pixel tile) is staged in LDS,
 // double buffered: the next chunk's window is fetched into registers while the
 // current one is consumed.  The per-angle constants (window start, tile-centre
@@ -80,12 +80,13 @@ struct Raw {
   unsigned w[kWords];
 };
 
-// Called by the group's first wave (t < 64) for the chunk starting at angle k0.
+// Called by the group's first wave (t < 64) for the chunk starting at angle k0;
+// angles from kend on (the end of the group's share) are not read.
 template <typename T>
 __device__ __forceinline__ void load_raw(Raw<T>& r, const BwdAngle* __restrict__ ang, int k0,
-                                         int t, int m) {
+                                         int t, int kend) {
   const int k = k0 + (t & 31);
-  if (k < m) {
+  if (k < kend) {
     const BwdAngle& A = ang[k];
     const void* src;
     if constexpr (sizeof(T) == 4) src = t < 32 ? (const void*)&A.c : (const void*)&A.Bf;
@@ -105,15 +106,16 @@ __device__ __forceinline__ double bits_to_double(unsigned lo, unsigned hi) {
 }
 
 // Ring entries of the chunk starting at angle k0 from its records (all lanes
-// of the group's first wave take part; lanes t < 32 write entry t).  The
-// float cosines are the float64 ones rounded to nearest, as in the table.
+// of the group's first wave take part; lanes t < 32 write entry t, for the
+// angles below kend).  The float cosines are the float64 ones rounded to
+// nearest, as in the table.
 template <typename T>
 __device__ __forceinline__ void fill_meta(Meta<T>* __restrict__ ring, const Raw<T>& r, int k0,
-                                          int t, int m, double Xc, double Yc, double hb) {
+                                          int t, int kend, double Xc, double Yc, double hb) {
   Raw<T> up;
 #pragma unroll
   for (int i = 0; i < Raw<T>::kWords; ++i) up.w[i] = __shfl_down(r.w[i], 32, 64);
-  if (t < kChunk && k0 + t < m) {
+  if (t < kChunk && k0 + t < kend) {
     const double c = bits_to_double(r.w[0], r.w[1]), s = bits_to_double(r.w[2], r.w[3]);
     Meta<T>& M = ring[t];
     const double Jc = fma(Xc, c, fma(Yc, s, hb));
@@ -197,14 +199,15 @@ __device__ __forceinline__ StageSrc stage_src(const BwdK<T>& a) {
 
 // rowoff = (t / 8) * nb, the offset of the thread's first row within a
 // chunk, taken once.  Elements [0, kPerRow) of sg are the first row's,
-// [kPerRow, 2 kPerRow) the second's.
+// [kPerRow, 2 kPerRow) the second's.  Rows from angle kend on (the end of the
+// group's share, at most m) load zeros.
 template <typename T, int MODE>
 __device__ __forceinline__ void stage_load(Stage<T, MODE>& sg, const StageSrc& src,
-                                           const Meta<T>* __restrict__ mt, int k0, int m, int nb,
-                                           unsigned rowoff, int t) {
+                                           const Meta<T>* __restrict__ mt, int k0, int kend,
+                                           int nb, unsigned rowoff, int t) {
   const int ka = t / kRowLanes, kb = ka + kRowHalf;
   const int ja = mt[ka].jw + (t % kRowLanes), jb = mt[kb].jw + (t % kRowLanes);
-  const bool rowa = ka < m - k0, rowb = kb < m - k0;
+  const bool rowa = ka < kend - k0, rowb = kb < kend - k0;
   sg.wa = rowa ? mt[ka].Wm : T(0);
   sg.wb = rowb ? mt[kb].Wm : T(0);
   // byte offsets of bins ja of angle k0 + ka and jb of angle k0 + kb (valid
@@ -389,21 +392,24 @@ __device__ __forceinline__ void backward_body(const BwdK<T>& a, const BlockPos h
   const double Yc = uniform(pos.y * kTile + 0.5 * (kTile - 1) - hc);
   const T dX = T(tx) - T(0.5 * (kTile - 1)), dY = T(ty) - T(0.5 * (kTile - 1));
   T acc0 = T(0), acc1 = T(0);
-  const int nchunks = (m + kChunk - 1) / kChunk;
-  const int steps = (nchunks + G - 1) / G;     // chunk steps, equal for every group
-  constexpr int kAhead = G * kChunk;           // angles from one of the group's chunks to the next
+  // Group grp takes the contiguous angles [kbeg, kend), an equal share (to
+  // one angle) of the m angles, in chunks of kChunk; every group makes the
+  // same number of chunk steps, each ending at a block barrier, so equal
+  // shares keep the groups from waiting on each other.
+  const int kbeg = (int)((long long)grp * m / G), kend = (int)((long long)(grp + 1) * m / G);
+  const int steps = ((m + G - 1) / G + kChunk - 1) / kChunk;
   // Records of the chunk two steps ahead (the group's first wave).
   const bool rawwave = t < 64;   // uniform per wave
   Raw<T> ahead;
   // prologue: the ring entries of the first two chunks, the records of the
   // third, then the first chunk's window straight into LDS
   {
-    const int k0 = grp * kChunk;
+    const int k0 = kbeg;
     Raw<T> r0, r1;
     if (rawwave) {
-      load_raw<T>(r0, a.ang, k0, t, m);
-      load_raw<T>(r1, a.ang, k0 + kAhead, t, m);
-      load_raw<T>(ahead, a.ang, k0 + 2 * kAhead, t, m);
+      load_raw<T>(r0, a.ang, k0, t, kend);
+      load_raw<T>(r1, a.ang, k0 + kChunk, t, kend);
+      load_raw<T>(ahead, a.ang, k0 + 2 * kChunk, t, kend);
     }
     if constexpr (MODE == BWD_CGLS) {
       // ||q||^2 from the forward projection's per-block partial sums (loaded
@@ -431,12 +437,12 @@ __device__ __forceinline__ void backward_body(const BwdK<T>& a, const BlockPos h
       alpha = uniform(alpha_v);
     }
     if (rawwave) {
-      fill_meta<T>(meta[grp][0], r0, k0, t, m, Xc, Yc, hb);
-      fill_meta<T>(meta[grp][1], r1, k0 + kAhead, t, m, Xc, Yc, hb);
+      fill_meta<T>(meta[grp][0], r0, k0, t, kend, Xc, Yc, hb);
+      fill_meta<T>(meta[grp][1], r1, k0 + kChunk, t, kend, Xc, Yc, hb);
     }
     __syncthreads();
     Stage<T, MODE> sg;
-    stage_load<T, MODE>(sg, src, meta[grp][0], grp * kChunk, m, nb, rowoff, t);
+    stage_load<T, MODE>(sg, src, meta[grp][0], k0, kend, nb, rowoff, t);
     if constexpr (MODE == BWD_CGLS) {
       // while the first window loads are in flight: delta = ||q||^2 +
       // lambda ||p||^2 and alpha = gamma / delta, the same in every block;
@@ -460,14 +466,13 @@ __device__ __forceinline__ void backward_body(const BwdK<T>& a, const BlockPos h
     set_priority(steps - 1 - st);   // chunk steps left
     const int cur = st & 1, nxt = cur ^ 1;
     const int mnext = mcur == 2 ? 0 : mcur + 1, mfill = mnext == 2 ? 0 : mnext + 1;
-    const int c = st * G + grp;                  // this group's chunk
-    const int k0 = c * kChunk, kc = max(0, min(kChunk, m - k0));
-    const int k1 = k0 + kAhead;                  // its next chunk
+    const int k0 = kbeg + st * kChunk, kc = max(0, min(kChunk, kend - k0));   // this group's chunk
+    const int k1 = k0 + kChunk;                  // its next chunk
     const bool more = st + 1 < steps;
     // start the next chunk's window loads; they are consumed after the
     // current chunk is done
     Stage<T, MODE> pre;
-    if (more) stage_load<T, MODE>(pre, src, meta[grp][mnext], k1, m, nb, rowoff, t);
+    if (more) stage_load<T, MODE>(pre, src, meta[grp][mnext], k1, kend, nb, rowoff, t);
     // compute the current chunk
     const Meta<T>* __restrict__ mt = meta[grp][mcur];
 #pragma unroll 4
@@ -486,10 +491,10 @@ __device__ __forceinline__ void backward_body(const BwdK<T>& a, const BlockPos h
     // ring entry of the chunk two steps ahead (its slot held the previous
     // chunk, read before the last barrier), then the next window into LDS,
     // then the records of the chunk three steps ahead
-    if (rawwave && k0 + 2 * kAhead < m)
-      fill_meta<T>(meta[grp][mfill], ahead, k0 + 2 * kAhead, t, m, Xc, Yc, hb);
+    if (rawwave && k0 + 2 * kChunk < kend)
+      fill_meta<T>(meta[grp][mfill], ahead, k0 + 2 * kChunk, t, kend, Xc, Yc, hb);
     if (more) stage_store<T, MODE>(pre, win[grp][nxt], alpha, t);
-    if (rawwave && k0 + 3 * kAhead < m) load_raw<T>(ahead, a.ang, k0 + 3 * kAhead, t, m);
+    if (rawwave && k0 + 3 * kChunk < kend) load_raw<T>(ahead, a.ang, k0 + 3 * kChunk, t, kend);
     mcur = mnext;
     __syncthreads();
   }
