@@ -419,12 +419,19 @@ def serve_run(reco, torch, S, rate, budget_gib, slots):
     srv.close()
     lat = [(v["t_done"] - v["t_submit"]) * 1e3 for v in res]
     span = max(v["t_done"] for v in res) - min(v["t_submit"] for v in res)
+    by_side = {}
+    for side in sorted({r.side for r in mix}):
+        idx = [i for i, r in enumerate(mix) if r.side == side]
+        by_side[str(side)] = {"count": len(idx),
+                              "latency_ms_p50_p99": percentiles([lat[i] for i in idx]),
+                              "solo_fifo_latency_ms_p50_p99": percentiles([fifo_lat[i] for i in idx])}
     return {
         "rate_per_s": round(rate, 3), "budget_gib": budget_gib,
         "recons_per_s": round(count / span, 3),
         "latency_ms_p50_p99": percentiles(lat),
         "queue_ms_p50_p99": percentiles([(v["t_admit"] - v["t_submit"]) * 1e3 for v in res]),
         "solo_fifo_latency_ms_p50_p99": percentiles(fifo_lat),
+        "by_side": by_side,
         "all_ok": all(v["status"] == "ok" for v in res),
         "results_equal_solo": bool(all(torch.equal(a, b) for a, b in zip(outs, S["xs"]))),
     }
