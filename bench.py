@@ -291,8 +291,10 @@ def batch_leg(reco, torch, count):
     bs = [gpu_sinogram(torch, g, r.n_ellipses, r.seed, r.noise) for g, r in zip(gs, mix)]
     xs = [g.new_image() for g in gs]
     nnz = {k: g.count_nnz() for k, g in geo.items()}
-    # warm-up: a small batch and one solo solve of every geometry
-    reco.solve_batch(gs[:8], bs[:8], xs[:8], tol=1e-3)
+    # warm-up: the whole batch (its workspaces, up to one per problem, then sit
+    # in the geometries' pools, so the timed runs do not allocate) and one solo
+    # solve of every geometry
+    reco.solve_batch(gs, bs, xs, tol=1e-3)
     seen = set()
     for g, b, x, r in zip(gs, bs, xs, mix):
         if (r.side, r.n_angles) not in seen:
