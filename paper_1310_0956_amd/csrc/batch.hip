@@ -366,7 +366,8 @@ class Engine {
   bool dirty_ = true;
   int clean_ticks_ = 0;
   hipGraphExec_t exec_ = nullptr;
-  DevTable t_fwd_, t_bwd_, t_wmg_;           // iteration work lists
+  FwdTables t_fwd_;                          // iteration work lists
+  DevTable t_bwd_, t_wmg_;
   DevTable t_init_, t_ib_, t_iw_;            // initialisation of new problems
   SolverState** d_sts_ = nullptr;
   Flag* d_flags_ = nullptr;

@@ -111,6 +111,7 @@ struct Geometry {
   int* d_fwd_order = nullptr;  // [ngroups * bin blocks] forward block run at each grid position
   void* d_fwd_blk = nullptr;   // [ngroups * bin blocks] FwdBlk record of each grid position
   int fwd_maxb = 0;
+  int fwd_halves = 1;          // threads per ray of the solo forward projector (1 or 2)
   BwdAngle* d_bwd = nullptr;   // [m]
   std::vector<FwdAngle> h_fwd;
   std::vector<BwdAngle> h_bwd;
@@ -290,9 +291,15 @@ void launch_state_init(SolverState* st, double tol, int max_iter, int fixed, dou
 
 // batched forms (float problems); the tables are filled by prepare_* and the
 // launches may be captured in a HIP graph and replayed.
-void prepare_forward_batch(DevTable& t, const std::vector<const Geometry*>& gs,
+// The batched forward projection is two launches: the problems whose solo
+// launch walks each ray with one thread, and those with two (small grids), so
+// that each problem's sums are those of its solo launch.
+struct FwdTables {
+  DevTable t[2];   // [threads per ray - 1]
+};
+void prepare_forward_batch(FwdTables& t, const std::vector<const Geometry*>& gs,
                            const std::vector<FwdArgs>& as, hipStream_t st);
-void launch_forward_batch(const DevTable& t, FwdMode mode, hipStream_t st);
+void launch_forward_batch(const FwdTables& t, FwdMode mode, hipStream_t st);
 void prepare_backward_batch(DevTable& t, const std::vector<const Geometry*>& gs,
                             const std::vector<BwdArgs>& as, hipStream_t st);
 void launch_backward_batch(const DevTable& t, BwdMode mode, hipStream_t st);

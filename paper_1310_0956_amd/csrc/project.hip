@@ -16,7 +16,8 @@
 //
 // Work decomposition: a block takes up to 8 neighbouring angles that share the
 // walk axis ("group") times 32 neighbouring detector bins, one ray per thread
-// (each wave: two angles, interleaved across its lanes).
+// (each wave: two angles, interleaved across its lanes); for grids too small
+// to fill the GPU, two threads per ray, each walking half of every band.
 // It walks the rows in bands: the columns the block's rays cross in a band
 // (known from the corner rays, since positions are linear in bin and row) are
 // staged in LDS with coalesced loads, double buffered through registers, and
@@ -44,9 +45,14 @@ constexpr int kStride = 126;    // LDS row stride of a staged band (elements); t
                                 // stay under 32 KB, so five blocks fit in a CU
 constexpr int kWinCols = 122;   // widest window staged in LDS; columns past the
                                 // window's width read zeros (guard columns)
-constexpr int kThreads = kSlots * kBins;
+constexpr int kRays = kSlots * kBins;            // rays per block
 constexpr int kLoadCols = 128;                    // staging: threads per row
-constexpr int kStageRows = kThreads / kLoadCols;  // rows loaded per staging pass
+// H threads per ray ("halves"): with H = 2 each walks half the rows of every
+// band, so a block has twice the waves, for grids too small to fill the GPU.
+template <int H>
+constexpr int kFwdThreads = kRays * H;
+template <int H>
+constexpr int kStageRows = kFwdThreads<H> / kLoadCols;   // rows loaded per staging pass
 
 template <typename T>
 constexpr int kBand = sizeof(T) == 4 ? 32 : 16;   // rows per staged band
@@ -99,6 +105,7 @@ struct Walk<float> {
     return (float)(unsigned)(p & 0xffffffffull) * 2.3283064365386963e-10f;
   }
   __device__ __forceinline__ void step() { p += dp; }
+  __device__ __forceinline__ void skip(int rows) { p += (unsigned long long)rows * dp; }
   __device__ __forceinline__ void shift_cols(int dc) {
     p -= (unsigned long long)(long long)dc << 32;
   }
@@ -119,6 +126,10 @@ struct Walk<double> {
   __device__ __forceinline__ double frac() const { return cur - floor(cur); }
   __device__ __forceinline__ void step() {
     ++r;
+    cur = fma((double)r, slope, P0);
+  }
+  __device__ __forceinline__ void skip(int rows) {
+    r += rows;
     cur = fma((double)r, slope, P0);
   }
   __device__ __forceinline__ void shift_cols(int dc) { off += dc; }
@@ -145,9 +156,14 @@ __device__ __forceinline__ T wM(const FwdAngle& a) {
 // weight (over the plateau) is clamp(lo * Bq + Cq, 0, 1) with lo the 32-bit
 // fraction of the position, Bq = -B 2^-32 and Cq = C + B/2 (the trapezoid
 // (1/2 - f) B + C).
+// TWO: rows r < split go to (acc0, acc1), the others to (acc0b, acc1b)
+// (split a multiple of 4, so no group of four rows straddles it; the choice
+// is a scalar branch); else every row goes to (acc0, acc1).
+template <bool TWO = false>
 __device__ __forceinline__ void band_lds(const float* __restrict__ w, Walk<float>& wk, int rows,
                                          unsigned width, float Bq, float Cq,
-                                         float& acc0, float& acc1) {
+                                         float& acc0, float& acc1, int split = 0,
+                                         float* acc0b = nullptr, float* acc1b = nullptr) {
   unsigned long long p = wk.p;
   const unsigned long long dp = wk.dp;
   int r = 0;
@@ -163,18 +179,32 @@ __device__ __forceinline__ void band_lds(const float* __restrict__ w, Walk<float
       p += dp;
       asm volatile("" : "+v"(p));   // one position register: keep LLVM from cloning it per row
     }
+    if (!TWO || r < split) {
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      acc0 = fmaf(w0[u], x0[u] - x1[u], acc0);
-      acc1 += x1[u];
+      for (int u = 0; u < 4; ++u) {
+        acc0 = fmaf(w0[u], x0[u] - x1[u], acc0);
+        acc1 += x1[u];
+      }
+    } else {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        *acc0b = fmaf(w0[u], x0[u] - x1[u], *acc0b);
+        *acc1b += x1[u];
+      }
     }
   }
   for (; r < rows; ++r) {
     const unsigned c = min((unsigned)(p >> 32), width);
     const float* q = w + r * kStride + c;
     const float x0 = q[0], x1 = q[1];
-    acc0 = fmaf(__builtin_amdgcn_fmed3f(fmaf((float)(unsigned)p, Bq, Cq), 0.0f, 1.0f), x0 - x1, acc0);
-    acc1 += x1;
+    const float w0 = __builtin_amdgcn_fmed3f(fmaf((float)(unsigned)p, Bq, Cq), 0.0f, 1.0f);
+    if (!TWO || r < split) {
+      acc0 = fmaf(w0, x0 - x1, acc0);
+      acc1 += x1;
+    } else {
+      *acc0b = fmaf(w0, x0 - x1, *acc0b);
+      *acc1b += x1;
+    }
     p += dp;
   }
   wk.p = p;
@@ -295,10 +325,20 @@ __global__ __launch_bounds__(256) void k_fwd_windows(const FwdAngle* __restrict_
   wins[(size_t)blk * maxb + b] = make_int2(c0, c1);
 }
 
-template <typename T, int MODE>
+template <typename T, int MODE, int H, bool PARTS>
 __device__ __forceinline__ void forward_body(const FwdK<T>& a, const BlockPos bp) {
   constexpr int BAND = kBand<T>;
-  constexpr int STAGE_PER = BAND / kStageRows;   // loads per thread per band
+  constexpr int NT = kFwdThreads<H>;
+  constexpr int SR = kStageRows<H>;
+  constexpr int STAGE_PER = BAND / SR;   // loads per thread per band
+  // PARTS: every band's rows are summed in two parts, [0, HB) and [HB, BAND),
+  // each in row order, and the parts are added at the end (first + second):
+  // with H = 2 a thread walks one part, with H = 1 both, into a second pair of
+  // sums, so both give bitwise the same result (a batched launch, one thread
+  // per ray, reproduces a solo solve that ran two).  Without PARTS (H = 1) the
+  // rows are summed in one pass.
+  constexpr int HB = BAND / 2;
+  static_assert(H == 1 || (H == 2 && PARTS), "one or two threads per ray");
   // The prologue runs at the top wave priority (latency bound; the band
   // loop lowers it with the work left).
   set_priority(3);
@@ -316,6 +356,8 @@ __device__ __forceinline__ void forward_body(const FwdK<T>& a, const BlockPos bp
   if constexpr (MODE == FWD_CGLS) alpha_v = (&a.st->alpha)[vzero];
   __shared__ T win[2][BAND * kStride];
   const int t = threadIdx.x;
+  const int tr = t % kRays;   // the thread's ray
+  const int half = __builtin_amdgcn_readfirstlane(t / kRays);   // its rows: [half HB, half HB + HB)
   const int n = a.n, nb = a.nb;
   // the block's record (setup table, one per grid position): its bins, rows,
   // walking axis and first band windows, then its angles
@@ -326,8 +368,8 @@ __device__ __forceinline__ void forward_body(const FwdK<T>& a, const BlockPos bp
   // ray of this thread: a wave holds two angles of the group, interleaved by
   // lane parity, so that each half-wave's LDS reads span about 16 bins' worth
   // of columns (fewer bank conflicts than 32 bins of one angle)
-  const int kl = rec->k[((t >> 6) << 1) + (t & 1)];
-  const int jown = jfirst + ((t >> 1) & 31);
+  const int kl = rec->k[((tr >> 6) << 1) + (tr & 1)];
+  const int jown = jfirst + ((tr >> 1) & 31);
   const bool valid = kl >= 0 && jown <= jlast;
   // invalid lanes shadow the block's first ray so that they stay in the window
   const int k = valid ? kl : k0;
@@ -344,7 +386,7 @@ __device__ __forceinline__ void forward_body(const FwdK<T>& a, const BlockPos bp
   // the table; those of bands 0 and 1 come with the record (zeros when absent).
   Window wcur{rec->w0x, rec->w0y};
   int2 wahead = make_int2(rec->w1x, rec->w1y);
-  // staging: thread loads column (t % kLoadCols) of rows (t / kLoadCols) + kStageRows * i;
+  // staging: thread loads column (t % kLoadCols) of rows (t / kLoadCols) + SR * i;
   // columns past the window's width are written as zeros (the guard columns);
   // threads with scol >= kStride only idle
   const int scol = t % kLoadCols;
@@ -362,7 +404,7 @@ __device__ __forceinline__ void forward_body(const FwdK<T>& a, const BlockPos bp
   T v0[STAGE_PER];
 #pragma unroll
   for (int i = 0; i < STAGE_PER; ++i) {
-    const int row = srow + kStageRows * i;
+    const int row = srow + SR * i;
     v0[i] = T(0);
     if (first_lds && scol <= wcur.c1 - wcur.c0)
       v0[i] = load_elem(rs, (unsigned)(wcur.c0 + kPad + scol) * sizeof(T), (lo + row) * rbytes,
@@ -372,14 +414,18 @@ __device__ __forceinline__ void forward_body(const FwdK<T>& a, const BlockPos bp
   const double P0 = fma((double)j, ang.inv, ang.A0);
   const T B = wB<T>(ang), C = wC<T>(ang), Wm = wM<T>(ang);
   const float Bq = (float)(-ang.B * 2.3283064365386963e-10), Cq = (float)(ang.C + 0.5 * ang.B);
-  T acc0 = T(0), acc1 = T(0);
+  T acc0 = T(0), acc1 = T(0);     // the thread's part (H = 2) or the first part (H = 1)
+  T acc0b = T(0), acc1b = T(0);   // H = 1: the second part
   Walk<T> wk;
   wk.init(fma((double)lo, ang.slope, P0), ang.slope, ang.dP);
+  // the second part's thread starts HB rows on, by the walker's own steps (the
+  // same positions as a walker that walks both parts)
+  if (half == 1) wk.skip(HB);
   if (nbands > 0) {
     if (first_lds) {
 #pragma unroll
       for (int i = 0; i < STAGE_PER; ++i)
-        if (stager) win[0][(srow + kStageRows * i) * kStride + scol] = v0[i];
+        if (stager) win[0][(srow + SR * i) * kStride + scol] = v0[i];
     }
     __syncthreads();
   }
@@ -402,7 +448,7 @@ __device__ __forceinline__ void forward_body(const FwdK<T>& a, const BlockPos bp
       if (next_lds) {
 #pragma unroll
         for (int i = 0; i < STAGE_PER; ++i) {
-          const int row = srow + kStageRows * i;
+          const int row = srow + SR * i;
           pre[i] = T(0);
           if (scol <= wnext.c1 - wnext.c0)
             pre[i] = load_elem(rs, (unsigned)(wnext.c0 + kPad + scol) * sizeof(T),
@@ -414,30 +460,82 @@ __device__ __forceinline__ void forward_body(const FwdK<T>& a, const BlockPos bp
     wk.shift_cols(wcur.c0 - cur_shift);
     cur_shift = wcur.c0;
     const int width = wcur.c1 - wcur.c0 + 1;
-    if (width <= kWinCols) {
-      if constexpr (sizeof(T) == 4)
-        band_lds(win[cur], wk, rows, (unsigned)width, Bq, Cq, acc0, acc1);
-      else
-        band_lds(win[cur], wk, rows, max(-2 - wcur.c0, 0), min(n - wcur.c0, width - 2), B, C,
-                 acc0, acc1);
+    // rows [p HB, p HB + HB) of the band (fewer in the last band) into (s0, s1)
+    auto part = [&](int p, T& s0, T& s1) {
+      const int rows_p = max(0, min(HB, rows - p * HB));
+      if (width <= kWinCols) {
+        const T* wband = win[cur] + p * HB * kStride;
+        if constexpr (sizeof(T) == 4)
+          band_lds(wband, wk, rows_p, (unsigned)width, Bq, Cq, s0, s1);
+        else
+          band_lds(wband, wk, rows_p, max(-2 - wcur.c0, 0), min(n - wcur.c0, width - 2), B, C,
+                   s0, s1);
+      } else {
+        band_mem<T>(rs, a.ld, n, rb + p * HB, rows_p, wcur.c0, wk, B, C, s0, s1);
+      }
+    };
+    if constexpr (!PARTS) {
+      if (width <= kWinCols) {
+        if constexpr (sizeof(T) == 4)
+          band_lds(win[cur], wk, rows, (unsigned)width, Bq, Cq, acc0, acc1);
+        else
+          band_lds(win[cur], wk, rows, max(-2 - wcur.c0, 0), min(n - wcur.c0, width - 2), B, C,
+                   acc0, acc1);
+      } else {
+        band_mem<T>(rs, a.ld, n, rb, rows, wcur.c0, wk, B, C, acc0, acc1);
+      }
+    } else if constexpr (H == 1) {
+      if constexpr (sizeof(T) == 4) {
+        if (width <= kWinCols) {   // both parts in one walk of the band
+          band_lds<true>(win[cur], wk, rows, (unsigned)width, Bq, Cq, acc0, acc1, HB, &acc0b,
+                         &acc1b);
+        } else {
+          part(0, acc0, acc1);
+          part(1, acc0b, acc1b);
+        }
+      } else {
+        part(0, acc0, acc1);
+        part(1, acc0b, acc1b);
+      }
     } else {
-      band_mem<T>(rs, a.ld, n, rb, rows, wcur.c0, wk, B, C, acc0, acc1);
+      part(half, acc0, acc1);
+      // past the other part's rows (only bands before the last have them all)
+      if (more) wk.skip(HB);
     }
     if (next_lds) {
 #pragma unroll
       for (int i = 0; i < STAGE_PER; ++i)
-        if (stager) win[nxt][(srow + kStageRows * i) * kStride + scol] = pre[i];
+        if (stager) win[nxt][(srow + SR * i) * kStride + scol] = pre[i];
     }
     wcur = wnext;
     __syncthreads();
   }
   set_priority(3);
+  if constexpr (!PARTS) {
+  } else if constexpr (H == 1) {
+    acc0 += acc0b;
+    acc1 += acc1b;
+  } else {
+    // the second part's sums, added by the thread of the first (the band loop
+    // ended with a barrier, so the window memory is free)
+    T* xch = &win[0][0];
+    if (half == 1) {
+      xch[tr] = acc0;
+      xch[kRays + tr] = acc1;
+    }
+    __syncthreads();
+    if (half == 0) {
+      acc0 += xch[tr];
+      acc1 += xch[kRays + tr];
+    }
+  }
+  const bool owner = valid && half == 0;   // the thread that stores its ray
   const T result = (T)a.h * (Wm * (acc0 + acc1));
   const size_t i = (size_t)k * nb + j;   // valid lanes only use it
   if constexpr (MODE == FWD_PLAIN) {
-    if (valid) a.out[i] = result;
+    if (owner) a.out[i] = result;
   } else if constexpr (MODE == FWD_SIRT) {
-    if (valid) a.out[i] = (T)((double)a.R[i] * ((double)a.b[i] - (double)result));
+    if (owner) a.out[i] = (T)((double)a.R[i] * ((double)a.b[i] - (double)result));
   } else if constexpr (MODE == FWD_CGLS) {
     // The residual update of the previous iteration, r -= alpha q_old (alpha
     // of that iteration, stored by the previous backprojection), then
@@ -446,33 +544,33 @@ __device__ __forceinline__ void forward_body(const FwdK<T>& a, const BlockPos bp
     // the following backprojection (kernel boundaries make it visible), which
     // forms delta and the step length alpha from it.
     double q = 0.0, r_new = 0.0;
-    if (valid) {
+    if (owner) {
       const double q_old = (double)a.out[i];
       r_new = (double)a.r[i] - uniform(alpha_v) * q_old;
       q = (double)(T)((double)result + a.st->beta * q_old);
     }
-    __shared__ double sh[kThreads / 64];
+    __shared__ double sh[NT / 64];
     double v[1] = {q * q};
-    block_sum<1, kThreads / 64>(v, sh);
+    block_sum<1, NT / 64>(v, sh);
     if (threadIdx.x == 0) a.part[bp.id()] = v[0];
-    if (valid) {
+    if (owner) {
       a.r[i] = (T)r_new;
       a.out[i] = (T)q;
     }
   }
 }
 
-template <typename T, int MODE>
-__global__ __launch_bounds__(kThreads) void k_forward(FwdK<T> a) {
-  forward_body<T, MODE>(a, grid_pos());
+template <typename T, int MODE, int H>
+__global__ __launch_bounds__(kFwdThreads<H>) void k_forward(FwdK<T> a) {
+  forward_body<T, MODE, H, H == 2>(a, grid_pos());
 }
 
-template <typename T, int MODE>
-__global__ __launch_bounds__(kThreads) void k_forward_batch(const FwdK<T>* __restrict__ args,
+template <typename T, int MODE, int H>
+__global__ __launch_bounds__(kFwdThreads<H>) void k_forward_batch(const FwdK<T>* __restrict__ args,
                                                             const int* __restrict__ start,
                                                             const int* __restrict__ gx, int count) {
   const int r = batch_find(start, count, blockIdx.x);
-  forward_body<T, MODE>(args[r], batch_pos(start, gx, r));
+  forward_body<T, MODE, H, H == 2>(args[r], batch_pos(start, gx, r));
 }
 
 // Nonzero count of W: one thread per ray, every row of the image, float64
@@ -579,11 +677,22 @@ void fwd_dispatch(const Geometry& g, FwdMode mode, const FwdArgs& a, hipStream_t
   }
   dim3 grid((g.nb + kBins - 1) / kBins, g.ngroups);
   FwdK<T> k = make_args<T>(g, a);
-  switch (mode) {
-    case FWD_PLAIN: hipLaunchKernelGGL((k_forward<T, FWD_PLAIN>), grid, dim3(kThreads), 0, st, k); break;
-    case FWD_CGLS: hipLaunchKernelGGL((k_forward<T, FWD_CGLS>), grid, dim3(kThreads), 0, st, k); break;
-    case FWD_SIRT: hipLaunchKernelGGL((k_forward<T, FWD_SIRT>), grid, dim3(kThreads), 0, st, k); break;
-    default: break;
+  if (g.fwd_halves == 2) {
+    const dim3 blk(kFwdThreads<2>);
+    switch (mode) {
+      case FWD_PLAIN: hipLaunchKernelGGL((k_forward<T, FWD_PLAIN, 2>), grid, blk, 0, st, k); break;
+      case FWD_CGLS: hipLaunchKernelGGL((k_forward<T, FWD_CGLS, 2>), grid, blk, 0, st, k); break;
+      case FWD_SIRT: hipLaunchKernelGGL((k_forward<T, FWD_SIRT, 2>), grid, blk, 0, st, k); break;
+      default: break;
+    }
+  } else {
+    const dim3 blk(kFwdThreads<1>);
+    switch (mode) {
+      case FWD_PLAIN: hipLaunchKernelGGL((k_forward<T, FWD_PLAIN, 1>), grid, blk, 0, st, k); break;
+      case FWD_CGLS: hipLaunchKernelGGL((k_forward<T, FWD_CGLS, 1>), grid, blk, 0, st, k); break;
+      case FWD_SIRT: hipLaunchKernelGGL((k_forward<T, FWD_SIRT, 1>), grid, blk, 0, st, k); break;
+      default: break;
+    }
   }
   HIP_CHECK(hipGetLastError());
 }
@@ -624,6 +733,11 @@ void build_forward_windows(Geometry& g, hipStream_t st) {
   int cus = 0;
   HIP_CHECK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, g.device));
   const size_t P = (size_t)std::max(cus, 1);
+  // Two threads per ray when the grid has fewer than 8 blocks per CU (a few
+  // resident blocks per CU, all started at once): twice the waves per SIMD to
+  // hide latencies.  Larger grids keep one thread per ray: fewer instructions
+  // per update, and their VALU issue is the limit.
+  g.fwd_halves = nblk < 8 * P ? 2 : 1;
   std::vector<int> order(nblk);
   constexpr size_t kXcds = 8;
   for (size_t base = 0; base < nblk; base += P) {
@@ -681,35 +795,45 @@ void launch_forward(const Geometry& g, FwdMode mode, const FwdArgs& a, hipStream
   else fwd_dispatch<float>(g, mode, a, st);
 }
 
-void prepare_forward_batch(DevTable& t, const std::vector<const Geometry*>& gs,
+void prepare_forward_batch(FwdTables& t, const std::vector<const Geometry*>& gs,
                            const std::vector<FwdArgs>& as, hipStream_t st) {
-  std::vector<FwdK<float>> host(gs.size());
-  std::vector<int> blocks(gs.size()), widths(gs.size());
-  for (size_t i = 0; i < gs.size(); ++i) {
-    if (gs[i]->f64) fail(RECO_EINVAL, "batched solves take float32 geometries");
-    host[i] = make_args<float>(*gs[i], as[i]);
-    widths[i] = (gs[i]->nb + kBins - 1) / kBins;
-    blocks[i] = widths[i] * gs[i]->ngroups;
+  for (int h = 1; h <= 2; ++h) {   // the problems' order is kept within each table
+    std::vector<FwdK<float>> host;
+    std::vector<int> blocks, widths;
+    for (size_t i = 0; i < gs.size(); ++i) {
+      if (gs[i]->f64) fail(RECO_EINVAL, "batched solves take float32 geometries");
+      if (gs[i]->fwd_halves != h) continue;
+      host.push_back(make_args<float>(*gs[i], as[i]));
+      widths.push_back((gs[i]->nb + kBins - 1) / kBins);
+      blocks.push_back(widths.back() * gs[i]->ngroups);
+    }
+    t.t[h - 1].upload(host.data(), sizeof(FwdK<float>), blocks, widths, st);
   }
-  t.upload(host.data(), sizeof(FwdK<float>), blocks, widths, st);
 }
 
-void launch_forward_batch(const DevTable& t, FwdMode mode, hipStream_t st) {
+template <int H>
+static void launch_forward_batch_h(const DevTable& t, FwdMode mode, hipStream_t st) {
   if (t.count == 0) return;
   TimedLaunch tl(TK_FORWARD, st);
   const auto* args = (const FwdK<float>*)t.args;
+  const dim3 blk(kFwdThreads<H>);
   switch (mode) {
     case FWD_PLAIN:
-      hipLaunchKernelGGL((k_forward_batch<float, FWD_PLAIN>), dim3(t.total_blocks), dim3(kThreads), 0,
-                         st, args, t.start, t.gx, t.count);
+      hipLaunchKernelGGL((k_forward_batch<float, FWD_PLAIN, H>), dim3(t.total_blocks), blk, 0, st,
+                         args, t.start, t.gx, t.count);
       break;
     case FWD_CGLS:
-      hipLaunchKernelGGL((k_forward_batch<float, FWD_CGLS>), dim3(t.total_blocks), dim3(kThreads), 0,
-                         st, args, t.start, t.gx, t.count);
+      hipLaunchKernelGGL((k_forward_batch<float, FWD_CGLS, H>), dim3(t.total_blocks), blk, 0, st,
+                         args, t.start, t.gx, t.count);
       break;
     default: fail(RECO_EINVAL, "unsupported batched forward mode");
   }
   HIP_CHECK(hipGetLastError());
+}
+
+void launch_forward_batch(const FwdTables& t, FwdMode mode, hipStream_t st) {
+  launch_forward_batch_h<1>(t.t[0], mode, st);
+  launch_forward_batch_h<2>(t.t[1], mode, st);
 }
 
 void launch_pad_transpose(const Geometry& g, const void* x, void* xP, void* xTP, hipStream_t st) {
