@@ -71,8 +71,8 @@ typedef struct reco_server_s* reco_server;
  * are one pixel wide.  wmg_levels = ell >= 1 levels of the WMG hierarchy
  * (Section 3.1.3); the packet transform has L = ell - 1 levels, needs
  * n % 2^L == 0 and L <= 5.  dtype is RECO_F32 or RECO_F64.  Size limits (the
- * kernels use 32-bit byte offsets): n * (n + 8) and n_angles * n_bins
- * elements each below 2^31 bytes, i.e. n <= 23166 in RECO_F32 (16380 in
+ * kernels use 32-bit byte offsets): (n + 32) * (n + 8) and n_angles * n_bins
+ * elements each below 2^31 bytes, i.e. n <= 23150 in RECO_F32 (16364 in
  * RECO_F64); larger descriptions are rejected with RECO_EINVAL. */
 typedef struct {
   int32_t n;

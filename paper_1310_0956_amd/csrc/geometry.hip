@@ -115,11 +115,13 @@ Geometry* create_geometry(const reco_geometry_desc& d, hipStream_t st) {
   const int L = d.wmg_levels - 1;
   if (d.n % (1 << L) != 0) fail(RECO_EINVAL, "n must be divisible by 2^(wmg_levels-1)");
   // The projectors address the padded image copies and the sinogram with
-  // 32-bit byte offsets (buffer loads): each must stay below 2^31 bytes.
+  // 32-bit byte offsets (buffer loads): each must stay below 2^31 bytes, the
+  // image copy with 32 rows to spare (a staged band's rows may run past the
+  // last row, and an offset past the end plus a row offset must not wrap).
   const double es = d.dtype == RECO_F64 ? 8.0 : 4.0;
-  if ((double)d.n * (d.n + 2 * kPad) * es >= 2147483648.0)
-    fail(RECO_EINVAL, "image too large: a padded image copy must stay below 2^31 bytes "
-                      "(n <= 23166 for RECO_F32, 16380 for RECO_F64)");
+  if ((double)(d.n + 32) * (d.n + 2 * kPad) * es >= 2147483648.0)
+    fail(RECO_EINVAL, "image too large: a padded image copy and 32 more rows must stay below "
+                      "2^31 bytes (n <= 23150 for RECO_F32, 16364 for RECO_F64)");
   if ((double)d.n_angles * d.n_bins * es >= 2147483648.0)
     fail(RECO_EINVAL, "sinogram too large: n_angles * n_bins * element size must stay below 2^31");
 

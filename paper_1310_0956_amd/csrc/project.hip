@@ -401,15 +401,14 @@ __device__ __forceinline__ void forward_body(const FwdK<T>& a, const BlockPos bp
   // the first band's loads, issued before the ray set-up waits for the
   // angle records
   const bool first_lds = nbands > 0 && wcur.c1 - wcur.c0 + 1 <= kWinCols;
+  // columns past the window (and a window not staged) read zeros from an
+  // offset past the end of the buffer: one select, then unconditional loads
+  const unsigned coff0 = first_lds && scol <= wcur.c1 - wcur.c0
+                             ? (unsigned)(wcur.c0 + kPad + scol) * (unsigned)sizeof(T)
+                             : kOutside;
   T v0[STAGE_PER];
 #pragma unroll
-  for (int i = 0; i < STAGE_PER; ++i) {
-    const int row = srow + SR * i;
-    v0[i] = T(0);
-    if (first_lds && scol <= wcur.c1 - wcur.c0)
-      v0[i] = load_elem(rs, (unsigned)(wcur.c0 + kPad + scol) * sizeof(T), (lo + row) * rbytes,
-                        T(0));
-  }
+  for (int i = 0; i < STAGE_PER; ++i) v0[i] = load_elem(rs, coff0, (lo + srow + SR * i) * rbytes, T(0));
   // the ray: walker and weight coefficients
   const double P0 = fma((double)j, ang.inv, ang.A0);
   const T B = wB<T>(ang), C = wC<T>(ang), Wm = wM<T>(ang);
@@ -446,14 +445,12 @@ __device__ __forceinline__ void forward_body(const FwdK<T>& a, const BlockPos bp
       wnext = Window{w1.x, w1.y};
       next_lds = wnext.c1 - wnext.c0 + 1 <= kWinCols;
       if (next_lds) {
+        const unsigned coff = scol <= wnext.c1 - wnext.c0
+                                  ? (unsigned)(wnext.c0 + kPad + scol) * (unsigned)sizeof(T)
+                                  : kOutside;
 #pragma unroll
-        for (int i = 0; i < STAGE_PER; ++i) {
-          const int row = srow + SR * i;
-          pre[i] = T(0);
-          if (scol <= wnext.c1 - wnext.c0)
-            pre[i] = load_elem(rs, (unsigned)(wnext.c0 + kPad + scol) * sizeof(T),
-                               (rb2 + row) * rbytes, T(0));
-        }
+        for (int i = 0; i < STAGE_PER; ++i)
+          pre[i] = load_elem(rs, coff, (rb2 + srow + SR * i) * rbytes, T(0));
       }
     }
     // walker columns relative to this band's window start

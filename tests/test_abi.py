@@ -43,8 +43,8 @@ def test_invalid_arguments_rejected_without_gpu_work():
     bad = [reco.GeometryDesc(0, 10, 10, 2, 0, 0), reco.GeometryDesc(16, 0, 10, 2, 0, 0),
            reco.GeometryDesc(16, 10, 10, 7, 0, 0), reco.GeometryDesc(18, 10, 10, 3, 0, 0),
            reco.GeometryDesc(16, 10, 10, 2, 5, 0), reco.GeometryDesc(16, 10, 10, 2, 0, 2),
-           # 32-bit byte offsets: padded image n (n + 8) and sinogram below 2^31 bytes
-           reco.GeometryDesc(23167, 1, 1, 1, 0, 0), reco.GeometryDesc(16381, 1, 1, 1, 1, 0),
+           # 32-bit byte offsets: padded image (n + 32) (n + 8) and sinogram below 2^31 bytes
+           reco.GeometryDesc(23151, 1, 1, 1, 0, 0), reco.GeometryDesc(16365, 1, 1, 1, 1, 0),
            reco.GeometryDesc(64, 1 << 15, 1 << 14, 1, 0, 0),
            reco.GeometryDesc(64, 1 << 14, 1 << 14, 1, 1, 0)]
     for d in bad:
