@@ -156,14 +156,9 @@ __device__ __forceinline__ T wM(const FwdAngle& a) {
 // weight (over the plateau) is clamp(lo * Bq + Cq, 0, 1) with lo the 32-bit
 // fraction of the position, Bq = -B 2^-32 and Cq = C + B/2 (the trapezoid
 // (1/2 - f) B + C).
-// TWO: rows r < split go to (acc0, acc1), the others to (acc0b, acc1b)
-// (split a multiple of 4, so no group of four rows straddles it; the choice
-// is a scalar branch); else every row goes to (acc0, acc1).
-template <bool TWO = false>
 __device__ __forceinline__ void band_lds(const float* __restrict__ w, Walk<float>& wk, int rows,
                                          unsigned width, float Bq, float Cq,
-                                         float& acc0, float& acc1, int split = 0,
-                                         float* acc0b = nullptr, float* acc1b = nullptr) {
+                                         float& acc0, float& acc1) {
   unsigned long long p = wk.p;
   const unsigned long long dp = wk.dp;
   int r = 0;
@@ -179,18 +174,10 @@ __device__ __forceinline__ void band_lds(const float* __restrict__ w, Walk<float
       p += dp;
       asm volatile("" : "+v"(p));   // one position register: keep LLVM from cloning it per row
     }
-    if (!TWO || r < split) {
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        acc0 = fmaf(w0[u], x0[u] - x1[u], acc0);
-        acc1 += x1[u];
-      }
-    } else {
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        *acc0b = fmaf(w0[u], x0[u] - x1[u], *acc0b);
-        *acc1b += x1[u];
-      }
+    for (int u = 0; u < 4; ++u) {
+      acc0 = fmaf(w0[u], x0[u] - x1[u], acc0);
+      acc1 += x1[u];
     }
   }
   for (; r < rows; ++r) {
@@ -198,13 +185,8 @@ __device__ __forceinline__ void band_lds(const float* __restrict__ w, Walk<float
     const float* q = w + r * kStride + c;
     const float x0 = q[0], x1 = q[1];
     const float w0 = __builtin_amdgcn_fmed3f(fmaf((float)(unsigned)p, Bq, Cq), 0.0f, 1.0f);
-    if (!TWO || r < split) {
-      acc0 = fmaf(w0, x0 - x1, acc0);
-      acc1 += x1;
-    } else {
-      *acc0b = fmaf(w0, x0 - x1, *acc0b);
-      *acc1b += x1;
-    }
+    acc0 = fmaf(w0, x0 - x1, acc0);
+    acc1 += x1;
     p += dp;
   }
   wk.p = p;
@@ -325,20 +307,17 @@ __global__ __launch_bounds__(256) void k_fwd_windows(const FwdAngle* __restrict_
   wins[(size_t)blk * maxb + b] = make_int2(c0, c1);
 }
 
-template <typename T, int MODE, int H, bool PARTS>
+template <typename T, int MODE, int H>
 __device__ __forceinline__ void forward_body(const FwdK<T>& a, const BlockPos bp) {
   constexpr int BAND = kBand<T>;
   constexpr int NT = kFwdThreads<H>;
   constexpr int SR = kStageRows<H>;
   constexpr int STAGE_PER = BAND / SR;   // loads per thread per band
-  // PARTS: every band's rows are summed in two parts, [0, HB) and [HB, BAND),
-  // each in row order, and the parts are added at the end (first + second):
-  // with H = 2 a thread walks one part, with H = 1 both, into a second pair of
-  // sums, so both give bitwise the same result (a batched launch, one thread
-  // per ray, reproduces a solo solve that ran two).  Without PARTS (H = 1) the
-  // rows are summed in one pass.
+  // H = 2: every band's rows are summed in two parts, [0, HB) by the ray's
+  // first thread and [HB, BAND) by its second, each in row order, and the
+  // parts are added at the end (first + second).  H = 1: one pass.
   constexpr int HB = BAND / 2;
-  static_assert(H == 1 || (H == 2 && PARTS), "one or two threads per ray");
+  static_assert(H == 1 || H == 2, "one or two threads per ray");
   // The prologue runs at the top wave priority (latency bound; the band
   // loop lowers it with the work left).
   set_priority(3);
@@ -413,8 +392,7 @@ __device__ __forceinline__ void forward_body(const FwdK<T>& a, const BlockPos bp
   const double P0 = fma((double)j, ang.inv, ang.A0);
   const T B = wB<T>(ang), C = wC<T>(ang), Wm = wM<T>(ang);
   const float Bq = (float)(-ang.B * 2.3283064365386963e-10), Cq = (float)(ang.C + 0.5 * ang.B);
-  T acc0 = T(0), acc1 = T(0);     // the thread's part (H = 2) or the first part (H = 1)
-  T acc0b = T(0), acc1b = T(0);   // H = 1: the second part
+  T acc0 = T(0), acc1 = T(0);     // the thread's sums (its part of every band for H = 2)
   Walk<T> wk;
   wk.init(fma((double)lo, ang.slope, P0), ang.slope, ang.dP);
   // the second part's thread starts HB rows on, by the walker's own steps (the
@@ -457,45 +435,23 @@ __device__ __forceinline__ void forward_body(const FwdK<T>& a, const BlockPos bp
     wk.shift_cols(wcur.c0 - cur_shift);
     cur_shift = wcur.c0;
     const int width = wcur.c1 - wcur.c0 + 1;
-    // rows [p HB, p HB + HB) of the band (fewer in the last band) into (s0, s1)
-    auto part = [&](int p, T& s0, T& s1) {
-      const int rows_p = max(0, min(HB, rows - p * HB));
+    // rows [r0, r0 + nrows) of the band into the thread's sums
+    auto walk = [&](int r0, int nrows) {
       if (width <= kWinCols) {
-        const T* wband = win[cur] + p * HB * kStride;
+        const T* wband = win[cur] + r0 * kStride;
         if constexpr (sizeof(T) == 4)
-          band_lds(wband, wk, rows_p, (unsigned)width, Bq, Cq, s0, s1);
+          band_lds(wband, wk, nrows, (unsigned)width, Bq, Cq, acc0, acc1);
         else
-          band_lds(wband, wk, rows_p, max(-2 - wcur.c0, 0), min(n - wcur.c0, width - 2), B, C,
-                   s0, s1);
-      } else {
-        band_mem<T>(rs, a.ld, n, rb + p * HB, rows_p, wcur.c0, wk, B, C, s0, s1);
-      }
-    };
-    if constexpr (!PARTS) {
-      if (width <= kWinCols) {
-        if constexpr (sizeof(T) == 4)
-          band_lds(win[cur], wk, rows, (unsigned)width, Bq, Cq, acc0, acc1);
-        else
-          band_lds(win[cur], wk, rows, max(-2 - wcur.c0, 0), min(n - wcur.c0, width - 2), B, C,
+          band_lds(wband, wk, nrows, max(-2 - wcur.c0, 0), min(n - wcur.c0, width - 2), B, C,
                    acc0, acc1);
       } else {
-        band_mem<T>(rs, a.ld, n, rb, rows, wcur.c0, wk, B, C, acc0, acc1);
+        band_mem<T>(rs, a.ld, n, rb + r0, nrows, wcur.c0, wk, B, C, acc0, acc1);
       }
-    } else if constexpr (H == 1) {
-      if constexpr (sizeof(T) == 4) {
-        if (width <= kWinCols) {   // both parts in one walk of the band
-          band_lds<true>(win[cur], wk, rows, (unsigned)width, Bq, Cq, acc0, acc1, HB, &acc0b,
-                         &acc1b);
-        } else {
-          part(0, acc0, acc1);
-          part(1, acc0b, acc1b);
-        }
-      } else {
-        part(0, acc0, acc1);
-        part(1, acc0b, acc1b);
-      }
+    };
+    if constexpr (H == 1) {
+      walk(0, rows);
     } else {
-      part(half, acc0, acc1);
+      walk(half * HB, max(0, min(HB, rows - half * HB)));   // fewer rows in the last band
       // past the other part's rows (only bands before the last have them all)
       if (more) wk.skip(HB);
     }
@@ -508,11 +464,7 @@ __device__ __forceinline__ void forward_body(const FwdK<T>& a, const BlockPos bp
     __syncthreads();
   }
   set_priority(3);
-  if constexpr (!PARTS) {
-  } else if constexpr (H == 1) {
-    acc0 += acc0b;
-    acc1 += acc1b;
-  } else {
+  if constexpr (H == 2) {
     // the second part's sums, added by the thread of the first (the band loop
     // ended with a barrier, so the window memory is free)
     T* xch = &win[0][0];
@@ -559,7 +511,7 @@ __device__ __forceinline__ void forward_body(const FwdK<T>& a, const BlockPos bp
 
 template <typename T, int MODE, int H>
 __global__ __launch_bounds__(kFwdThreads<H>) void k_forward(FwdK<T> a) {
-  forward_body<T, MODE, H, H == 2>(a, grid_pos());
+  forward_body<T, MODE, H>(a, grid_pos());
 }
 
 template <typename T, int MODE, int H>
@@ -567,7 +519,7 @@ __global__ __launch_bounds__(kFwdThreads<H>) void k_forward_batch(const FwdK<T>*
                                                             const int* __restrict__ start,
                                                             const int* __restrict__ gx, int count) {
   const int r = batch_find(start, count, blockIdx.x);
-  forward_body<T, MODE, H, H == 2>(args[r], batch_pos(start, gx, r));
+  forward_body<T, MODE, H>(args[r], batch_pos(start, gx, r));
 }
 
 // Nonzero count of W: one thread per ray, every row of the image, float64
