@@ -245,24 +245,33 @@ __device__ __forceinline__ void y_stages(T (&w)[1 << L], const T (&sgn)[L > 0 ? 
 // the coefficients land in the in-place layout of the apply (x frequency u at
 // tile column u, y frequency v at tile row v).
 //
-// Symmetries of the geometry cut the work by four.  Bins are centred on the
-// rotation centre, so the tile mirrored through the image centre sees, at
-// every angle, the mirrored weights of bin nb - 1 - j (its pixels rotated by
-// half a turn, which changes only the signs of the Walsh coefficients): equal
-// sums, so only the tiles t < ceil(tiles / 2) (row-major index) are computed.
-// With m even, angle k + m/2 is angle k turned by a quarter: its weights on
-// tile (tx, ty) are angle k's on tile (ty, N - 1 - tx) turned by a quarter, so
-// its coefficient (u, v) there is angle k's (v, u) up to sign; the angles
-// k < m/2 are summed and k_diag_assemble adds the turned tile's transposed
-// sums.
-// One launch covers angles [k0, k1): the running float64 sums S, compact per
-// computed tile ([tile][row][column]), are kept in memory between launches
-// (first: start from zero).  The angle order, hence the result, does not
-// depend on how the angles are split over launches.
+// Symmetries of the geometry cut the work by about eight (N tiles per side;
+// tile (tx, ty); each map below changes only the signs of the Walsh
+// coefficients, which are squared, or exchanges u and v).
+//  - Bins are centred on the rotation centre, so the tile mirrored through the
+//    image centre sees, at every angle, the mirrored weights of bin
+//    nb - 1 - j: equal sums, so only the tiles t < ceil(N^2 / 2) (row-major
+//    index) are computed.
+//  - Angle m - k is angle k reflected left-right: on tile T it gives angle k's
+//    sums of X T = (N - 1 - tx, ty).
+//  - With m even, angle k + m/2 is angle k turned by a quarter (on T: angle
+//    k's sums of R T = (ty, N - 1 - tx), u and v exchanged), and so angle
+//    m/2 - k is angle k reflected about the diagonal (on T: angle k's sums of
+//    the transposed tile (ty, tx), u and v exchanged).
+// So with A = sum of d_k over k = 0 .. floor(m/4) (m even) or
+// k = 0 .. (m - 1)/2 (m odd), angle 0 and, when 4 divides m, angle m/4
+// weighted 1/2 (the maps send them to themselves or to each other),
+//   d(T) = A(T) + A(X T)                                   (m odd)
+//   d(T) = A(T) + A(X T) + A(T^T)^T + A(R T)^T              (m even).
+// k_diag_assemble forms these sums.
+// One launch covers angles [k0, k1) of that range: the running float64 sums,
+// compact per computed tile ([tile][row][column]), are kept in memory between
+// launches (first: start from zero).  The angle order, hence the result, does
+// not depend on how the angles are split over launches.
 template <typename T, int L>
 __global__ __launch_bounds__(256) void k_packet_diag(const BwdAngle* __restrict__ ang, double* S,
                                                      int n, int nb, int k0, int k1, int first,
-                                                     int nh) {
+                                                     int nh, int khalf) {
   constexpr int Tt = 1 << L;
   constexpr int TPW = 64 / Tt;   // tiles per wave
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -326,8 +335,9 @@ __global__ __launch_bounds__(256) void k_packet_diag(const BwdAngle* __restrict_
 #pragma unroll
       for (int x = 0; x < Tt; ++x) part[x] = fma(w[x], w[x], part[x]);
     }
+    const double wk = (k == 0 || k == khalf) ? 0.5 : 1.0;   // exact scaling
 #pragma unroll
-    for (int x = 0; x < Tt; ++x) acc[x] += (double)part[x];
+    for (int x = 0; x < Tt; ++x) acc[x] += wk * (double)part[x];
   }
   if (active) {
 #pragma unroll
@@ -335,12 +345,12 @@ __global__ __launch_bounds__(256) void k_packet_diag(const BwdAngle* __restrict_
   }
 }
 
-// d (float64, in-place layout) from the sums of the computed tiles: tile t's
-// own (or its mirror's) plus, with paired angles, the transposed sums of the
-// quarter-turned tile, times h^2 4^-L.
+// d (float64, in-place layout) from the sums A of the computed tiles (a tile
+// past them is its mirror's): A(T) + A(X T), plus A(T^T)^T + A(R T)^T when m
+// is even, times h^2 4^-L.
 template <int L>
 __global__ __launch_bounds__(256) void k_diag_assemble(const double* __restrict__ S,
-                                                       double* __restrict__ d64, int n, int pair,
+                                                       double* __restrict__ d64, int n, int even,
                                                        double scale) {
   constexpr int Tt = 1 << L;
   const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
@@ -348,9 +358,13 @@ __global__ __launch_bounds__(256) void k_diag_assemble(const double* __restrict_
   const int iy = (int)(i / n), ix = (int)(i % n);
   const int N = n >> L, nt = N * N, nh = (nt + 1) / 2;
   const int tx = ix >> L, ty = iy >> L, u = ix & (Tt - 1), v = iy & (Tt - 1);
-  auto computed = [&](int t) { return t < nh ? t : nt - 1 - t; };
-  double sum = S[((size_t)computed(ty * N + tx) * Tt + v) * Tt + u];
-  if (pair) sum += S[((size_t)computed((N - 1 - tx) * N + ty) * Tt + u) * Tt + v];
+  auto tile = [&](int t) { return S + (size_t)(t < nh ? t : nt - 1 - t) * Tt * Tt; };
+  double sum = tile(ty * N + tx)[v * Tt + u];              // A(T)
+  sum += tile(ty * N + (N - 1 - tx))[v * Tt + u];          // A(X T)
+  if (even) {
+    sum += tile(tx * N + ty)[u * Tt + v];                  // A(T^T)^T, T^T = (ty, tx)
+    sum += tile((N - 1 - tx) * N + ty)[u * Tt + v];        // A(R T)^T, R T = (ty, N - 1 - tx)
+  }
   d64[i] = sum * scale;
 }
 
@@ -370,8 +384,11 @@ template <typename T, int L>
 void diag_launch_L(Geometry& g, hipStream_t st) {
   const int ntiles = (g.n >> L) * (g.n >> L);
   const int nh = (ntiles + 1) / 2;
-  const int pair = g.m % 2 == 0 ? 1 : 0;
-  const int mh = pair ? g.m / 2 : g.m;
+  const int even = g.m % 2 == 0 ? 1 : 0;
+  // angles summed: 0 .. floor(m/4) (m even) or 0 .. (m - 1)/2 (m odd); angle 0
+  // and, when 4 divides m, angle m/4 with weight 1/2
+  const int mh = even ? g.m / 4 + 1 : (g.m - 1) / 2 + 1;
+  const int khalf = g.m % 4 == 0 ? g.m / 4 : -1;
   double* S = (double*)g.d_diag;
   const int tiles_per_block = 4 * (64 >> L);
   const int blocks = (nh + tiles_per_block - 1) / tiles_per_block;
@@ -384,13 +401,13 @@ void diag_launch_L(Geometry& g, hipStream_t st) {
     const int k1 = std::min(mh, k0 + per_launch);
     TimedLaunch tl(TK_PACKET_DIAG, st);
     hipLaunchKernelGGL((k_packet_diag<T, L>), dim3(blocks), dim3(256), 0, st, g.d_bwd, S, g.n,
-                       g.nb, k0, k1, k0 == 0 ? 1 : 0, nh);
+                       g.nb, k0, k1, k0 == 0 ? 1 : 0, nh, khalf);
     HIP_CHECK(hipGetLastError());
   }
   const size_t N = (size_t)g.n * g.n;
   const unsigned eblocks = (unsigned)((N + 255) / 256);
   hipLaunchKernelGGL((k_diag_assemble<L>), dim3(eblocks), dim3(256), 0, st, S, g.d_diag64, g.n,
-                     pair, g.h * g.h / (double)(1u << (2 * L)));
+                     even, g.h * g.h / (double)(1u << (2 * L)));
   HIP_CHECK(hipGetLastError());
   hipLaunchKernelGGL((k_diag_round<T>), dim3(eblocks), dim3(256), 0, st, g.d_diag64, (T*)g.d_diag,
                      N);

@@ -1,7 +1,7 @@
 """Pins of the oracle WMG preconditioners.
 
   * the packet diagonal equals diag(H_L W^T W H_L^T) from dense matrices (+ lam),
-    and has the mirror and quarter-turn symmetries of the geometry;
+    and has the mirror, reflection and quarter-turn symmetries of the geometry;
   * additive-exact inverts K when K = H_L^T B H_L with B block diagonal over packets;
   * additive-diagonal inverts K when B is diagonal;
   * the hybrid cycle also inverts such K exactly (the packet subspaces are then
@@ -51,21 +51,31 @@ def _quadrant_to_tile_local(dq, L):
 
 
 @pytest.mark.parametrize("n,m,nb,L", [(16, 8, 23, 2), (12, 8, 17, 2), (12, 7, 17, 2),
-                                      (24, 12, 35, 3), (6, 4, 9, 0)])
+                                      (24, 12, 35, 3), (6, 4, 9, 0), (16, 6, 16, 1),
+                                      (16, 2, 23, 2), (16, 1, 23, 2), (20, 9, 29, 2)])
 def test_packet_diagonal_symmetries(n, m, nb, L):
-    """The geometry's symmetries, on which the device computation of d rests:
-    with bins centred on the rotation centre, a tile and its mirror through the
-    image centre have equal sums at every angle, and (m even) angle k + m/2 is
-    angle k turned by a quarter, so on tile (tx, ty) it gives angle k's sums of
-    tile (ty, N - 1 - tx) with the packet row and column exchanged.  Summing the
-    angles k < m/2 (all angles for odd m) over the tiles t < ceil(N^2 / 2) and
-    assembling must give the full diagonal."""
+    """The geometry's symmetries, on which the device computation of d rests.
+    With bins centred on the rotation centre a tile and its mirror through the
+    image centre have equal sums at every angle; angle m - k is angle k
+    reflected left-right (on tile (tx, ty): angle k's sums of X T =
+    (N - 1 - tx, ty)); with m even, angle m/2 - k is angle k reflected about
+    the diagonal (the transposed tile (ty, tx), packet row and column
+    exchanged) and angle k + m/2 is angle k turned by a quarter (tile
+    R T = (ty, N - 1 - tx), row and column exchanged).  So with A the sum over
+    angles 0 .. floor(m/4) (m even) or 0 .. (m - 1)/2 (m odd), angle 0 and, when
+    4 divides m, angle m/4 weighted 1/2, over the tiles t < ceil(N^2 / 2):
+    d(T) = A(T) + A(X T) (+ A(T^T)^T + A(R T)^T for m even)."""
     g = Geometry(n, m, nb)
     full = _quadrant_to_tile_local(wmg.packet_diagonal_by_angles(g, L), L)
-    pair = m % 2 == 0
-    mh = m // 2 if pair else m
-    half = _quadrant_to_tile_local(
-        wmg.packet_diagonal([angle_block(g, k) for k in range(mh)], n, L), L)
+    if m % 2 == 0:
+        wts = {k: 1.0 for k in range(m // 4 + 1)}
+        if m % 4 == 0:
+            wts[m // 4] = 0.5
+    else:
+        wts = {k: 1.0 for k in range((m - 1) // 2 + 1)}
+    wts[0] = 0.5
+    A = sum(w * _quadrant_to_tile_local(wmg.packet_diagonal([angle_block(g, k)], n, L), L)
+            for k, w in wts.items())
     T, N = 1 << L, n >> L
     nt = N * N
     nh = (nt + 1) // 2
@@ -73,18 +83,18 @@ def test_packet_diagonal_symmetries(n, m, nb, L):
     def tile(t):   # the computed tile standing for tile t, its sums
         t = t if t < nh else nt - 1 - t
         ty, tx = divmod(t, N)
-        return half[ty * T:(ty + 1) * T, tx * T:(tx + 1) * T]
+        return A[ty * T:(ty + 1) * T, tx * T:(tx + 1) * T]
 
     got = np.empty_like(full)
     for ty in range(N):
         for tx in range(N):
-            blk = tile(ty * N + tx).copy()
-            if pair:
-                blk += tile((N - 1 - tx) * N + ty).T
+            blk = tile(ty * N + tx) + tile(ty * N + (N - 1 - tx))
+            if m % 2 == 0:
+                blk = blk + tile(tx * N + ty).T + tile((N - 1 - tx) * N + ty).T
             got[ty * T:(ty + 1) * T, tx * T:(tx + 1) * T] = blk
     assert np.allclose(got, full, rtol=1e-12, atol=1e-14 * full.max())
-    # the identity is not vacuous: the angles differ and tiles differ
-    assert not np.allclose(half, full - half, rtol=1e-3) or not pair
+    # fewer angles than m are summed once m > 2
+    assert len(wts) < m or m <= 2
 
 
 def _block_diag_K(n, L, seed, diagonal=False):
