@@ -452,8 +452,8 @@ __device__ __forceinline__ void forward_body(const FwdK<T>& a, const BlockPos bp
       walk(0, rows);
     } else {
       walk(half * HB, max(0, min(HB, rows - half * HB)));   // fewer rows in the last band
-      // past the other part's rows (only bands before the last have them all)
-      if (more) wk.skip(HB);
+      // past the other part's rows (after the last band the walker is not used)
+      wk.skip(HB);
     }
     if (next_lds) {
 #pragma unroll
