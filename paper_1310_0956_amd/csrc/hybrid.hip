@@ -22,9 +22,9 @@
 //   else:     e_LL = cycle(P LL, r);  r' = r - A_P e_LL  (on the LH, HL, HH
 //             positions);  e_id = cycle(P id, r') for id = LH, HL, HH.
 //
-// Set-up (float64, on a float64 copy of the geometry): A_p[i][j] is the
-// packet-p coefficient of tile j of K v_i, v_i the packet-p basis image of tile
-// i (its Walsh pattern times 2^-L), one Galerkin apply per unknown; then a
+// Set-up (float64): A_p[i][j] = v_j^T K v_i, v_i the packet-p basis image of
+// tile i (its Walsh pattern times 2^-L), formed for every packet and tile pair
+// in the packet domain from the projection weights (k_galerkin_pairs); then a
 // Cholesky factorisation of every block in natural order in which pivots at
 // most 1e-12 of the largest coarsest diagonal entry are dropped (not
 // eliminated; zero correction), then X = L^-1 row by row and its transpose.
@@ -176,33 +176,120 @@ __global__ __launch_bounds__(256) void k_leaf(LeafArgs a) {
 // ---------------------------------------------------------------------------
 // Set-up kernels (float64)
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ double walsh_sign(int qy, int qx, int py, int px) {
-  return ((__popc(qy & py) + __popc(qx & px)) & 1) ? -1.0 : 1.0;
-}
-
-// The basis image of packet (py, px) on tile (ty, tx) (set) or zeros (clear),
-// written into both padded copies; one thread per tile pixel.
-__global__ void k_basis(double* P, double* TP, int ld, int TS, int ty, int tx, int py, int px,
-                        int set) {
-  const int qy = threadIdx.x / TS, qx = threadIdx.x - qy * TS;
-  const double v = set ? walsh_sign(qy, qx, py, px) / (double)TS : 0.0;
-  const size_t iy = (size_t)ty * TS + qy, ix = (size_t)tx * TS + qx;
-  P[iy * ld + kPad + ix] = v;
-  TP[ix * ld + kPad + iy] = v;
-}
-
-// row[j] = packet (py, px) coefficient of tile j of img; one thread per tile.
-__global__ __launch_bounds__(256) void k_galerkin_row(const double* __restrict__ img, int n,
-                                                      int tiles, int TS, int py, int px,
-                                                      double* __restrict__ row) {
-  const int j = blockIdx.x * 256 + threadIdx.x;
-  if (j >= tiles * tiles) return;
-  const int ty = j / tiles, tx = j - ty * tiles;
-  double s = 0.0;
-  for (int qy = 0; qy < TS; ++qy)
-    for (int qx = 0; qx < TS; ++qx)
-      s += walsh_sign(qy, qx, py, px) * img[((size_t)ty * TS + qy) * n + (size_t)tx * TS + qx];
-  row[j] = s / (double)TS;
+// The Galerkin blocks directly in the packet domain.  The basis vector of
+// packet p = (py, px) on tile i is the Hadamard pattern (-1)^(popc(qy & py) +
+// popc(qx & px)) / TS on the tile's pixels (qy, qx), and these vectors are
+// orthonormal, so A_p[i][i'] = <W v_p,i, W v_p,i'> + lambda [i = i'].  Row
+// (k, j) of W holds h times the trapezoid weight of each pixel's bin distance
+// (the weight of the projectors), so (W v_p,i) at ray (k, j) is h / TS times
+// the Hadamard coefficient p of the tile's weights for that ray, and
+//   A_p[i][i'] = h^2 / 4^L  sum_k sum_j H_p(i; k, j) H_p(i'; k, j)
+// over the rays that meet both tiles.  One group of TS lanes per tile pair
+// i <= i' (pairs in row order, so a wave's pairs share i and have
+// neighbouring i'): lane y holds row y of each tile's weights, transformed
+// along x in registers and along y across the group's lanes (lane y, register
+// x ends with coefficient (py, px) = (y, x)); the products are summed over the
+// angles in order and the common bins in order.  Every entry is written by
+// one group, A_p[i'][i] = A_p[i][i'] beside it.
+template <int L>
+__global__ __launch_bounds__(256) void k_galerkin_pairs(const BwdAngle* __restrict__ ang,
+                                                        double* __restrict__ S, int n, int nb,
+                                                        int m, long long npairs, double scale,
+                                                        double lambda) {
+  constexpr int Tt = 1 << L;
+  constexpr int PPW = 64 / Tt;   // pairs per wave
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const long long pq = ((long long)blockIdx.x * 4 + wv) * PPW + lane / Tt;
+  const int y = lane & (Tt - 1);
+  const int tiles = n / Tt, c = tiles * tiles;
+  const bool active = pq < npairs;
+  // pair index -> (a, b), a <= b: row a starts at a c - a (a - 1) / 2
+  long long a = 0, b = 0;
+  if (active) {
+    const double cc2 = 2.0 * c + 1.0;
+    a = (long long)((cc2 - sqrt(cc2 * cc2 - 8.0 * (double)pq)) * 0.5);
+    auto start = [&](long long r) { return r * c - r * (r - 1) / 2; };
+    while (a > 0 && start(a) > pq) --a;
+    while (a + 1 < c && start(a + 1) <= pq) ++a;
+    b = pq - start(a) + a;
+  }
+  const double hc = 0.5 * (n - 1), hb = 0.5 * (nb - 1);
+  const int tya = (int)(a / tiles), txa = (int)(a % tiles);
+  const int tyb = (int)(b / tiles), txb = (int)(b % tiles);
+  const double Xa = txa * Tt + 0.5 * (Tt - 1) - hc, Ya = tya * Tt + 0.5 * (Tt - 1) - hc;
+  const double Xb = txb * Tt + 0.5 * (Tt - 1) - hc, Yb = tyb * Tt + 0.5 * (Tt - 1) - hc;
+  const double dY = y - 0.5 * (Tt - 1);
+  double sgn[L > 0 ? L : 1];   // y stage q: +1 keeps u + v (low lane), -1 gives u - v (high lane)
+#pragma unroll
+  for (int q = 0; q < L; ++q) sgn[q] = ((y >> q) & 1) ? -1.0 : 1.0;
+  double acc[Tt];
+#pragma unroll
+  for (int x = 0; x < Tt; ++x) acc[x] = 0.0;
+  // Hadamard coefficients of the weights of bin j on the tile whose row y has
+  // bin coordinates J[x]
+  auto coeffs = [&](const double (&J)[Tt], int j, double inv_uv, double cc, double wm,
+                    double (&w)[Tt]) {
+#pragma unroll
+    for (int x = 0; x < Tt; ++x) w[x] = fmin(fmax(fma(-fabs((double)j - J[x]), inv_uv, cc), 0.0), wm);
+#pragma unroll
+    for (int q = 0; q < L; ++q) {   // along x, in registers
+#pragma unroll
+      for (int x = 0; x < Tt; ++x) {
+        if (!(x & (1 << q))) {
+          const double u = w[x], v = w[x | (1 << q)];
+          w[x] = u + v;
+          w[x | (1 << q)] = u - v;
+        }
+      }
+    }
+    // along y, across the group's lanes
+    if constexpr (L > 0) {
+#pragma unroll
+      for (int x = 0; x < Tt; ++x) w[x] = fma(sgn[0], w[x], xor_lane<1>(w[x]));
+    }
+    if constexpr (L > 1) {
+#pragma unroll
+      for (int x = 0; x < Tt; ++x) w[x] = fma(sgn[1], w[x], xor_lane<2>(w[x]));
+    }
+    if constexpr (L > 2) {
+#pragma unroll
+      for (int x = 0; x < Tt; ++x) w[x] = fma(sgn[2], w[x], xor_lane<4>(w[x]));
+    }
+  };
+  if (active) {
+    for (int k = 0; k < m; ++k) {
+      const BwdAngle A = ang[k];
+      const double Jca = fma(Xa, A.c, fma(Ya, A.s, hb));
+      const double Jcb = fma(Xb, A.c, fma(Yb, A.s, hb));
+      // bins with nonzero weight on a tile: |j - J| < Tt (u + v) / 2 around its centre
+      const double reach = Tt * A.half_u_plus_v;
+      const int jlo = max(max((int)floor(Jca - reach), (int)floor(Jcb - reach)), 0);
+      const int jhi = min(min((int)ceil(Jca + reach), (int)ceil(Jcb + reach)), nb - 1);
+      if (jlo > jhi) continue;   // uniform within the pair's lanes
+      double Ja[Tt], Jb[Tt];
+      const double bya = fma(dY, A.s, Jca), byb = fma(dY, A.s, Jcb);
+#pragma unroll
+      for (int x = 0; x < Tt; ++x) {
+        const double dX = x - 0.5 * (Tt - 1);
+        Ja[x] = fma(dX, A.c, bya);
+        Jb[x] = fma(dX, A.c, byb);
+      }
+      for (int j = jlo; j <= jhi; ++j) {
+        double wa[Tt], wb[Tt];
+        coeffs(Ja, j, A.inv_uv_d, A.cc_d, A.Wmax, wa);
+        coeffs(Jb, j, A.inv_uv_d, A.cc_d, A.Wmax, wb);
+#pragma unroll
+        for (int x = 0; x < Tt; ++x) acc[x] = fma(wa[x], wb[x], acc[x]);
+      }
+    }
+#pragma unroll
+    for (int x = 0; x < Tt; ++x) {
+      const long long p = (long long)y * Tt + x;
+      const double v = scale * acc[x] + (a == b ? lambda : 0.0);
+      S[(p * c + a) * c + b] = v;
+      if (a != b) S[(p * c + b) * c + a] = v;
+    }
+  }
 }
 
 // thr = kHybridDropRel * (largest diagonal entry of all blocks); one block.
@@ -433,67 +520,39 @@ std::unique_ptr<HybridFactors> build_factors(Geometry& g, double lambda, hipStre
   f->lambda = lambda;
   const int c = f->c, TS = f->TS;
   const size_t blk = (size_t)f->leaves * c * c;
-  // the Galerkin applies run on a float64 copy of the geometry (no WMG levels)
-  std::unique_ptr<Geometry> twin;
-  Geometry* g64 = &g;
-  if (!g.f64) {
-    reco_geometry_desc d = g.desc;
-    d.dtype = RECO_F64;
-    d.wmg_levels = 1;
-    twin.reset(create_geometry(d, st));
-    g64 = twin.get();
-  }
-  double *S = nullptr, *Lf = nullptr, *P = nullptr, *TP = nullptr, *sino = nullptr,
-         *img = nullptr, *thr = nullptr;
+  double *S = nullptr, *Lf = nullptr, *thr = nullptr;
   int* cnt = nullptr;
   auto release = [&]() {
-    for (void* p : {(void*)S, (void*)Lf, (void*)P, (void*)TP, (void*)sino, (void*)img,
-                    (void*)thr, (void*)cnt})
+    for (void* p : {(void*)S, (void*)Lf, (void*)thr, (void*)cnt})
       if (p) (void)hipFree(p);
   };
   try {
     dalloc((void**)&S, sizeof(double) * blk);
     dalloc((void**)&Lf, sizeof(double) * blk);
-    dalloc((void**)&P, sizeof(double) * g64->padded_elems());
-    dalloc((void**)&TP, sizeof(double) * g64->padded_elems());
-    dalloc((void**)&sino, sizeof(double) * g64->M());
-    dalloc((void**)&img, sizeof(double) * g64->N());
     dalloc((void**)&thr, sizeof(double));
     dalloc((void**)&cnt, sizeof(int));
     launch_fill(Lf, blk, true, 0.0, st);
-    launch_fill(P, g64->padded_elems(), true, 0.0, st);
-    launch_fill(TP, g64->padded_elems(), true, 0.0, st);
-    // Galerkin blocks: row i of block p = packet-p coefficients of K v_i
-    const unsigned rgrid = (unsigned)((c + 255) / 256);
-    for (int py = 0; py < TS; ++py) {
-      for (int px = 0; px < TS; ++px) {
-        double* Sp = S + (size_t)(py * TS + px) * c * c;
-        for (int i = 0; i < c; ++i) {
-          const int ty = i / f->tiles, tx = i - ty * f->tiles;
-          hipLaunchKernelGGL(k_basis, dim3(1), dim3(TS * TS), 0, st, P, TP, g64->ld, TS, ty, tx,
-                             py, px, 1);
-          FwdArgs fa{};
-          fa.imgP = P;
-          fa.imgTP = TP;
-          fa.out = sino;
-          launch_forward(*g64, FWD_PLAIN, fa, st);
-          BwdArgs ba{};
-          ba.sino = sino;
-          ba.out = img;
-          ba.x = P;
-          ba.x_ld = g64->ld;
-          ba.x_off = kPad;
-          ba.sa = 1.0;
-          ba.sx = lambda;
-          launch_backward(*g64, BWD_AXPY, ba, st);
-          hipLaunchKernelGGL(k_galerkin_row, dim3(rgrid), dim3(256), 0, st, (const double*)img,
-                             g64->n, f->tiles, TS, py, px, Sp + (size_t)i * c);
-          hipLaunchKernelGGL(k_basis, dim3(1), dim3(TS * TS), 0, st, P, TP, g64->ld, TS, ty, tx,
-                             py, px, 0);
-        }
-        HIP_CHECK(hipGetLastError());
-      }
+    // Galerkin blocks, every packet and tile pair in one launch (float64)
+    const long long npairs = (long long)c * (c + 1) / 2;
+    const long long per_block = 4LL * (64 / TS);
+    const unsigned grid = (unsigned)((npairs + per_block - 1) / per_block);
+    const double scale = g.h * g.h / (double)(TS * TS);
+    switch (g.L) {
+      case 1:
+        hipLaunchKernelGGL(k_galerkin_pairs<1>, dim3(grid), dim3(256), 0, st, g.d_bwd, S, g.n,
+                           g.nb, g.m, npairs, scale, lambda);
+        break;
+      case 2:
+        hipLaunchKernelGGL(k_galerkin_pairs<2>, dim3(grid), dim3(256), 0, st, g.d_bwd, S, g.n,
+                           g.nb, g.m, npairs, scale, lambda);
+        break;
+      case 3:
+        hipLaunchKernelGGL(k_galerkin_pairs<3>, dim3(grid), dim3(256), 0, st, g.d_bwd, S, g.n,
+                           g.nb, g.m, npairs, scale, lambda);
+        break;
+      default: fail(RECO_EINVAL, "unsupported number of hybrid levels");
     }
+    HIP_CHECK(hipGetLastError());
     hipLaunchKernelGGL(k_drop_threshold, dim3(1), dim3(256), 0, st, (const double*)S, c,
                        f->leaves, thr);
     for (int k = 0; k < c; ++k) {
