@@ -310,37 +310,59 @@ __global__ __launch_bounds__(256) void k_drop_threshold(const double* __restrict
   if (threadIdx.x == 0) *thr = kHybridDropRel * sh[0];
 }
 
-// Step k of the right-looking Cholesky factorisation of every block (lower
-// triangles): the column L[i][k] = S[i][k] / sqrt(S[k][k]) and the trailing
-// update S[i][j] -= S[i][k] S[j][k] / S[k][k] (k < j <= i), unless the pivot
-// is at most thr (dropped: column k of L stays zero, nothing is eliminated).
-// Column k of S is only read in this step.
+// Step k of the right-looking Cholesky factorisation of every block, worked
+// in the upper triangle (S is formed symmetric, and row k is contiguous where
+// column k is strided): the column L[i][k] = S[k][i] / sqrt(S[k][k]) and the
+// trailing update S[j][i] -= S[k][i] S[k][j] / S[k][k] (k < j <= i), unless
+// the pivot is at most thr (dropped: column k of L stays zero, nothing is
+// eliminated).  Row k of S is only read in this step.  Grid: x over i >= k,
+// y over j >= k.
 __global__ void k_chol_step(double* __restrict__ S, double* __restrict__ Lf, int c, int k,
                             const double* __restrict__ thr) {
-  const int j = k + blockIdx.x * 16 + threadIdx.x;
-  const int i = k + blockIdx.y * 16 + threadIdx.y;
+  if (blockIdx.y > blockIdx.x) return;   // j > i throughout the block
+  const int i = k + blockIdx.x * 16 + threadIdx.x;
+  const int j = k + blockIdx.y * 16 + threadIdx.y;
   if (i >= c || j > i) return;
   const size_t off = (size_t)blockIdx.z * c * c;
   const double piv = S[off + (size_t)k * c + k];
   if (!(piv > *thr)) return;
-  const double sik = S[off + (size_t)i * c + k];
+  const double sik = S[off + (size_t)k * c + i];
   if (j == k) Lf[off + (size_t)i * c + k] = sik / sqrt(piv);
-  else S[off + (size_t)i * c + j] -= sik * S[off + (size_t)j * c + k] / piv;
+  else S[off + (size_t)j * c + i] -= sik * S[off + (size_t)k * c + j] / piv;
 }
 
-// Row i of X = L^-1 for every block: X[i][j] = (delta_ij - sum_{j<=k<i}
-// L[i][k] X[k][j]) / L[i][i] for j <= i; a dropped unknown (L[i][i] = 0) has
-// a zero row, and a zero column follows.  X starts zero.
-__global__ __launch_bounds__(256) void k_trinv_row(const double* __restrict__ Lf,
-                                                   double* __restrict__ X, int c, int i) {
-  const int j = blockIdx.x * 256 + threadIdx.x;
-  if (j > i) return;
-  const size_t off = (size_t)blockIdx.y * c * c;
-  const double lii = Lf[off + (size_t)i * c + i];
-  if (lii == 0.0) return;
-  double s = i == j ? 1.0 : 0.0;
-  for (int k = j; k < i; ++k) s -= Lf[off + (size_t)i * c + k] * X[off + (size_t)k * c + j];
-  X[off + (size_t)i * c + j] = s / lii;
+// Step k of X = L^-1 for every block, right looking: T starts as the
+// identity, and X[k][j] = T[k][j] / L[k][k] once the rows before k have been
+// eliminated, so step k subtracts L[i][k] X[k][j] from T[i][j] for i > k,
+// j <= k (the same terms in the same order as X[i][j] = (delta_ij -
+// sum_{j<=m<i} L[i][m] X[m][j]) / L[i][i]); the launch also turns row k - 1 of
+// T into X (row k is only read, rows past k only written).  A dropped unknown
+// (L[k][k] = 0) gives a zero row, and a zero column follows.  Launch k = c
+// finishes the last row.  Grid: x over j <= k, y over rows k - 1 .. c - 1.
+__global__ void k_trinv_step(const double* __restrict__ Lf, double* __restrict__ T, int c,
+                             int k) {
+  const int j = blockIdx.x * 16 + threadIdx.x;
+  const int i = k - 1 + blockIdx.y * 16 + threadIdx.y;
+  if (i >= c || i == k) return;
+  const size_t off = (size_t)blockIdx.z * c * c;
+  if (i == k - 1) {   // row k - 1 is complete: X[k-1][j] = T[k-1][j] / L[k-1][k-1]
+    if (j > i) return;
+    const double lii = Lf[off + (size_t)i * c + i];
+    T[off + (size_t)i * c + j] = lii != 0.0 ? T[off + (size_t)i * c + j] / lii : 0.0;
+    return;
+  }
+  if (j > k) return;
+  const double lkk = Lf[off + (size_t)k * c + k];
+  if (lkk == 0.0) return;   // X[k][j] = 0: nothing to subtract
+  const double xkj = T[off + (size_t)k * c + j] / lkk;
+  T[off + (size_t)i * c + j] -= Lf[off + (size_t)i * c + k] * xkj;
+}
+
+// T = I for every block (the start of k_trinv_step).
+__global__ __launch_bounds__(256) void k_identity_blocks(double* __restrict__ T, int c) {
+  const size_t off = (size_t)blockIdx.z * c * c;
+  const int j = blockIdx.x * 16 + threadIdx.x, i = blockIdx.y * 16 + threadIdx.y;
+  if (i < c && j < c) T[off + (size_t)i * c + j] = i == j ? 1.0 : 0.0;
 }
 
 __global__ __launch_bounds__(256) void k_transpose_blocks(const double* __restrict__ X,
@@ -563,10 +585,16 @@ std::unique_ptr<HybridFactors> build_factors(Geometry& g, double lambda, hipStre
     HIP_CHECK(hipGetLastError());
     // X = L^-1 into S's storage, then X^T into L's
     double* X = S;
-    launch_fill(X, blk, true, 0.0, st);
-    for (int i = 0; i < c; ++i)
-      hipLaunchKernelGGL(k_trinv_row, dim3((unsigned)((i + 256) / 256), f->leaves), dim3(256), 0,
-                         st, (const double*)Lf, X, c, i);
+    {
+      const unsigned sd = (unsigned)((c + 15) / 16);
+      hipLaunchKernelGGL(k_identity_blocks, dim3(sd, sd, f->leaves), dim3(16, 16), 0, st, X, c);
+    }
+    for (int k = 0; k <= c; ++k) {
+      const unsigned gx = (unsigned)(std::min(k, c - 1) / 16 + 1);
+      const unsigned gy = (unsigned)((c - (k - 1) + 15) / 16);
+      hipLaunchKernelGGL(k_trinv_step, dim3(gx, gy, f->leaves), dim3(16, 16), 0, st,
+                         (const double*)Lf, X, c, k);
+    }
     HIP_CHECK(hipGetLastError());
     double* XT = Lf;
     const unsigned side = (unsigned)((c + 15) / 16);
