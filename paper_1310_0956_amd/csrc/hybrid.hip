@@ -310,55 +310,161 @@ __global__ __launch_bounds__(256) void k_drop_threshold(const double* __restrict
   if (threadIdx.x == 0) *thr = kHybridDropRel * sh[0];
 }
 
-// Step k of the right-looking Cholesky factorisation of every block, worked
-// in the upper triangle (S is formed symmetric, and row k is contiguous where
-// column k is strided): the column L[i][k] = S[k][i] / sqrt(S[k][k]) and the
-// trailing update S[j][i] -= S[k][i] S[k][j] / S[k][k] (k < j <= i), unless
-// the pivot is at most thr (dropped: column k of L stays zero, nothing is
-// eliminated).  Row k of S is only read in this step.  Grid: x over i >= k,
-// y over j >= k.
-__global__ void k_chol_step(double* __restrict__ S, double* __restrict__ Lf, int c, int k,
-                            const double* __restrict__ thr) {
-  if (blockIdx.y > blockIdx.x) return;   // j > i throughout the block
-  const int i = k + blockIdx.x * 16 + threadIdx.x;
-  const int j = k + blockIdx.y * 16 + threadIdx.y;
-  if (i >= c || j > i) return;
-  const size_t off = (size_t)blockIdx.z * c * c;
-  const double piv = S[off + (size_t)k * c + k];
-  if (!(piv > *thr)) return;
-  const double sik = S[off + (size_t)k * c + i];
-  if (j == k) Lf[off + (size_t)i * c + k] = sik / sqrt(piv);
-  else S[off + (size_t)j * c + i] -= sik * S[off + (size_t)k * c + j] / piv;
-}
+// The Cholesky factorisation of every block, right looking and worked in the
+// upper triangle (S is formed symmetric, and row k is contiguous where column
+// k is strided).  Step k writes the column L[i][k] = S[k][i] / sqrt(S[k][k])
+// and updates S[j][i] -= S[k][i] S[k][j] / S[k][k] for k < j <= i, unless the
+// pivot is at most thr (dropped: column k of L stays zero, nothing is
+// eliminated); row k is final after step k - 1.  The steps go in panels of
+// kPanel: k_chol_panel applies a panel's steps to the panel rows, k_chol_trail
+// applies them to the rows after it, so every entry takes the same updates in
+// the same order as step by step while the trailing matrix is read once per
+// panel.
+constexpr int kPanel = 16;
 
-// Step k of X = L^-1 for every block, right looking: T starts as the
-// identity, and X[k][j] = T[k][j] / L[k][k] once the rows before k have been
-// eliminated, so step k subtracts L[i][k] X[k][j] from T[i][j] for i > k,
-// j <= k (the same terms in the same order as X[i][j] = (delta_ij -
-// sum_{j<=m<i} L[i][m] X[m][j]) / L[i][i]); the launch also turns row k - 1 of
-// T into X (row k is only read, rows past k only written).  A dropped unknown
-// (L[k][k] = 0) gives a zero row, and a zero column follows.  Launch k = c
-// finishes the last row.  Grid: x over j <= k, y over rows k - 1 .. c - 1.
-__global__ void k_trinv_step(const double* __restrict__ Lf, double* __restrict__ T, int c,
-                             int k) {
-  const int j = blockIdx.x * 16 + threadIdx.x;
-  const int i = k - 1 + blockIdx.y * 16 + threadIdx.y;
-  if (i >= c || i == k) return;
-  const size_t off = (size_t)blockIdx.z * c * c;
-  if (i == k - 1) {   // row k - 1 is complete: X[k-1][j] = T[k-1][j] / L[k-1][k-1]
-    if (j > i) return;
-    const double lii = Lf[off + (size_t)i * c + i];
-    T[off + (size_t)i * c + j] = lii != 0.0 ? T[off + (size_t)i * c + j] / lii : 0.0;
-    return;
+// Panel K0 .. K0 + P - 1: one thread per column i >= K0 holds that column of
+// the panel rows in registers; the pivots and couplings S[k][j] of the panel
+// come from its diagonal block, factorised in LDS by every workgroup alike.
+// Grid: x over columns, y over blocks.
+__global__ __launch_bounds__(256) void k_chol_panel(double* __restrict__ S,
+                                                    double* __restrict__ Lf, int c, int K0,
+                                                    const double* __restrict__ thr) {
+  __shared__ double D[kPanel][kPanel + 1];
+  const size_t off = (size_t)blockIdx.y * c * c;
+  const int P = min(kPanel, c - K0);
+  const double th = *thr;
+  const int t = threadIdx.x, dr = t / kPanel, dq = t % kPanel;
+  const bool mine = dr < P && dq < P && dq >= dr;
+  if (mine) D[dr][dq] = S[off + (size_t)(K0 + dr) * c + K0 + dq];
+  __syncthreads();
+  for (int r = 0; r + 1 < P; ++r) {   // writes rows past r, reads row r
+    const double piv = D[r][r];
+    if (mine && dr > r && piv > th) D[dr][dq] -= D[r][dq] * D[r][dr] / piv;
+    __syncthreads();
   }
-  if (j > k) return;
-  const double lkk = Lf[off + (size_t)k * c + k];
-  if (lkk == 0.0) return;   // X[k][j] = 0: nothing to subtract
-  const double xkj = T[off + (size_t)k * c + j] / lkk;
-  T[off + (size_t)i * c + j] -= Lf[off + (size_t)i * c + k] * xkj;
+  const int i = K0 + blockIdx.x * 256 + t;
+  if (i >= c) return;
+  const int rows = min(P, i - K0 + 1);   // panel rows k <= i
+  double v[kPanel];
+#pragma unroll
+  for (int r = 0; r < kPanel; ++r)
+    v[r] = r < rows ? S[off + (size_t)(K0 + r) * c + i] : 0.0;
+#pragma unroll
+  for (int r = 0; r < kPanel; ++r) {
+    if (r >= rows) break;
+    const double piv = D[r][r];
+    if (!(piv > th)) continue;
+    const double sik = v[r];
+    Lf[off + (size_t)i * c + K0 + r] = sik / sqrt(piv);
+#pragma unroll
+    for (int q = r + 1; q < kPanel; ++q)
+      if (q < rows) v[q] -= sik * D[r][q] / piv;
+  }
+#pragma unroll
+  for (int r = 0; r < kPanel; ++r)
+    if (r < rows) S[off + (size_t)(K0 + r) * c + i] = v[r];
 }
 
-// T = I for every block (the start of k_trinv_step).
+// The rows K1 <= j <= i after panel K0 (K1 = K0 + P): 16 x 16 tiles of the
+// upper triangle, the panel rows over the tile's columns and rows staged in
+// LDS.  Grid: x over column tiles, y over row tiles, z over blocks.
+__global__ __launch_bounds__(256) void k_chol_trail(double* __restrict__ S, int c, int K0,
+                                                    const double* __restrict__ thr) {
+  if (blockIdx.y > blockIdx.x) return;   // below the diagonal throughout
+  __shared__ double A[kPanel][16], B[kPanel][16], pv[kPanel];
+  const size_t off = (size_t)blockIdx.z * c * c;
+  const int P = min(kPanel, c - K0), K1 = K0 + P;
+  const int tx = threadIdx.x, ty = threadIdx.y;
+  const int i0 = K1 + (int)blockIdx.x * 16, j0 = K1 + (int)blockIdx.y * 16;
+  if (ty < P) {
+    A[ty][tx] = i0 + tx < c ? S[off + (size_t)(K0 + ty) * c + i0 + tx] : 0.0;
+    B[ty][tx] = j0 + tx < c ? S[off + (size_t)(K0 + ty) * c + j0 + tx] : 0.0;
+  }
+  if (ty == 0 && tx < P) pv[tx] = S[off + (size_t)(K0 + tx) * c + K0 + tx];
+  __syncthreads();
+  const int i = i0 + tx, j = j0 + ty;
+  if (i >= c || j > i) return;
+  const double th = *thr;
+  double v = S[off + (size_t)j * c + i];
+  for (int r = 0; r < P; ++r) {
+    const double piv = pv[r];
+    if (piv > th) v -= A[r][tx] * B[r][ty] / piv;
+  }
+  S[off + (size_t)j * c + i] = v;
+}
+
+// X = L^-1 for every block, right looking: T starts as the identity, and
+// X[k][j] = T[k][j] / L[k][k] once the rows before k have been eliminated;
+// step k then subtracts L[i][k] X[k][j] from T[i][j] for i > k, j <= k (the
+// same terms in the same order as X[i][j] = (delta_ij - sum_{j<=m<i} L[i][m]
+// X[m][j]) / L[i][i]).  A dropped unknown (L[k][k] = 0) gives a zero row of X
+// and subtracts nothing.  In panels as the factorisation: k_trinv_panel
+// finishes the panel rows, k_trinv_trail updates the rows after them.
+
+// Panel K0 .. K0 + P - 1: one thread per column j < K1 holds that column of
+// the panel rows in registers, runs the panel's steps on them and writes them
+// as rows of X.  Grid: x over columns, y over blocks.
+__global__ __launch_bounds__(256) void k_trinv_panel(const double* __restrict__ Lf,
+                                                     double* __restrict__ T, int c, int K0) {
+  __shared__ double D[kPanel][kPanel + 1];   // D[q][r] = L[K0 + q][K0 + r]
+  const size_t off = (size_t)blockIdx.y * c * c;
+  const int P = min(kPanel, c - K0), K1 = K0 + P;
+  const int t = threadIdx.x;
+  {
+    const int q = t / kPanel, r = t % kPanel;
+    if (q < P && r < P) D[q][r] = Lf[off + (size_t)(K0 + q) * c + K0 + r];
+  }
+  __syncthreads();
+  const int j = (int)blockIdx.x * 256 + t;
+  if (j >= K1) return;
+  double v[kPanel];
+#pragma unroll
+  for (int r = 0; r < kPanel; ++r) v[r] = r < P ? T[off + (size_t)(K0 + r) * c + j] : 0.0;
+#pragma unroll
+  for (int r = 0; r < kPanel; ++r) {
+    if (r >= P) break;
+    if (j > K0 + r) continue;   // X[k][j] = 0 above the diagonal: T stays as it is
+    const double lkk = D[r][r];
+    if (lkk == 0.0) {
+      v[r] = 0.0;
+      continue;
+    }
+    const double x = v[r] / lkk;
+    v[r] = x;
+#pragma unroll
+    for (int q = r + 1; q < kPanel; ++q)
+      if (q < P) v[q] -= D[q][r] * x;
+  }
+#pragma unroll
+  for (int r = 0; r < kPanel; ++r)
+    if (r < P) T[off + (size_t)(K0 + r) * c + j] = v[r];
+}
+
+// The rows i >= K1 after panel K0, columns j < K1, in 16 x 16 tiles: L over
+// the tile's rows and the panel's X rows over its columns staged in LDS.
+// Grid: x over column tiles, y over row tiles, z over blocks.
+__global__ __launch_bounds__(256) void k_trinv_trail(const double* __restrict__ Lf,
+                                                     double* __restrict__ T, int c, int K0) {
+  __shared__ double A[16][kPanel + 1];   // A[y][r] = L[i0 + y][K0 + r]
+  __shared__ double B[kPanel][16];       // B[r][x] = X[K0 + r][j0 + x]
+  __shared__ double dg[kPanel];
+  const size_t off = (size_t)blockIdx.z * c * c;
+  const int P = min(kPanel, c - K0), K1 = K0 + P;
+  const int tx = threadIdx.x, ty = threadIdx.y;
+  const int j0 = (int)blockIdx.x * 16, i0 = K1 + (int)blockIdx.y * 16;
+  A[ty][tx] = i0 + ty < c && tx < P ? Lf[off + (size_t)(i0 + ty) * c + K0 + tx] : 0.0;
+  B[ty][tx] = ty < P && j0 + tx < K1 ? T[off + (size_t)(K0 + ty) * c + j0 + tx] : 0.0;
+  if (ty == 0 && tx < P) dg[tx] = Lf[off + (size_t)(K0 + tx) * c + K0 + tx];
+  __syncthreads();
+  const int i = i0 + ty, j = j0 + tx;
+  if (i >= c || j >= K1) return;
+  double v = T[off + (size_t)i * c + j];
+  for (int r = 0; r < P; ++r)
+    if (j <= K0 + r && dg[r] != 0.0) v -= A[ty][r] * B[r][tx];
+  T[off + (size_t)i * c + j] = v;
+}
+
+// T = I for every block (the start of the inverse).
 __global__ __launch_bounds__(256) void k_identity_blocks(double* __restrict__ T, int c) {
   const size_t off = (size_t)blockIdx.z * c * c;
   const int j = blockIdx.x * 16 + threadIdx.x, i = blockIdx.y * 16 + threadIdx.y;
@@ -577,10 +683,15 @@ std::unique_ptr<HybridFactors> build_factors(Geometry& g, double lambda, hipStre
     HIP_CHECK(hipGetLastError());
     hipLaunchKernelGGL(k_drop_threshold, dim3(1), dim3(256), 0, st, (const double*)S, c,
                        f->leaves, thr);
-    for (int k = 0; k < c; ++k) {
-      const unsigned side = (unsigned)((c - k + 15) / 16);
-      hipLaunchKernelGGL(k_chol_step, dim3(side, side, f->leaves), dim3(16, 16), 0, st, S, Lf, c,
-                         k, (const double*)thr);
+    for (int K0 = 0; K0 < c; K0 += kPanel) {
+      const int rest = c - K0 - std::min(kPanel, c - K0);
+      hipLaunchKernelGGL(k_chol_panel, dim3((unsigned)((c - K0 + 255) / 256), f->leaves),
+                         dim3(256), 0, st, S, Lf, c, K0, (const double*)thr);
+      if (rest > 0) {
+        const unsigned side = (unsigned)((rest + 15) / 16);
+        hipLaunchKernelGGL(k_chol_trail, dim3(side, side, f->leaves), dim3(16, 16), 0, st, S, c,
+                           K0, (const double*)thr);
+      }
     }
     HIP_CHECK(hipGetLastError());
     // X = L^-1 into S's storage, then X^T into L's
@@ -589,11 +700,14 @@ std::unique_ptr<HybridFactors> build_factors(Geometry& g, double lambda, hipStre
       const unsigned sd = (unsigned)((c + 15) / 16);
       hipLaunchKernelGGL(k_identity_blocks, dim3(sd, sd, f->leaves), dim3(16, 16), 0, st, X, c);
     }
-    for (int k = 0; k <= c; ++k) {
-      const unsigned gx = (unsigned)(std::min(k, c - 1) / 16 + 1);
-      const unsigned gy = (unsigned)((c - (k - 1) + 15) / 16);
-      hipLaunchKernelGGL(k_trinv_step, dim3(gx, gy, f->leaves), dim3(16, 16), 0, st,
-                         (const double*)Lf, X, c, k);
+    for (int K0 = 0; K0 < c; K0 += kPanel) {
+      const int K1 = K0 + std::min(kPanel, c - K0), rest = c - K1;
+      hipLaunchKernelGGL(k_trinv_panel, dim3((unsigned)((K1 + 255) / 256), f->leaves), dim3(256),
+                         0, st, (const double*)Lf, X, c, K0);
+      if (rest > 0)
+        hipLaunchKernelGGL(k_trinv_trail,
+                           dim3((unsigned)((K1 + 15) / 16), (unsigned)((rest + 15) / 16), f->leaves),
+                           dim3(16, 16), 0, st, (const double*)Lf, X, c, K0);
     }
     HIP_CHECK(hipGetLastError());
     double* XT = Lf;
