@@ -27,7 +27,8 @@
 // in the packet domain from the projection weights (k_galerkin_pairs); then a
 // Cholesky factorisation of every block in natural order in which pivots at
 // most 1e-12 of the largest coarsest diagonal entry are dropped (not
-// eliminated; zero correction), then X = L^-1 row by row and its transpose.
+// eliminated; zero correction), then X = L^-1 and its transpose; both run
+// right looking in panels of 16 steps.
 #include <cmath>
 #include <map>
 #include <memory>
