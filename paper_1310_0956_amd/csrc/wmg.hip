@@ -223,6 +223,11 @@ void wmg_launch(const Geometry& g, WmgMode mode, const WmgArgs& a, hipStream_t s
   }
 }
 
+// The unit clamp, which the compiler folds into the producing FMA's output
+// clamp modifier.
+__device__ __forceinline__ float unit_clamp(float v) { return __builtin_amdgcn_fmed3f(v, 0.0f, 1.0f); }
+__device__ __forceinline__ double unit_clamp(double v) { return fmin(fmax(v, 0.0), 1.0); }
+
 // y stages of the transform: stage b exchanges with lane y ^ 2^b
 template <typename T, int L, int B = 0>
 __device__ __forceinline__ void y_stages(T (&w)[1 << L], const T (&sgn)[L > 0 ? L : 1]) {
@@ -297,9 +302,13 @@ __global__ __launch_bounds__(256) void k_packet_diag(const BwdAngle* __restrict_
     const double Jt = fma(Xt, A.c, fma(Yt, A.s, hb));
     const double jbase = floor(Jt);
     const T rel = (T)(Jt - jbase);
-    T c, s, Bq, Cq, Wm;
-    if constexpr (sizeof(T) == 4) { c = A.cf; s = A.sf; Bq = A.inv_uv_f; Cq = A.cc_f; Wm = A.Wmaxf; }
-    else { c = A.c; s = A.s; Bq = A.inv_uv_d; Cq = A.cc_d; Wm = A.Wmax; }
+    T c, s;
+    if constexpr (sizeof(T) == 4) { c = A.cf; s = A.sf; }
+    else { c = A.c; s = A.s; }
+    // the trapezoid w = clamp(cc - dist inv_uv, 0, Wmax) divided by its
+    // plateau: the unit clamp is the weight FMA's output clamp, and Wmax^2
+    // scales the angle's sums of squares
+    const T Bn = (T)(A.inv_uv_d / A.Wmax), Cn = (T)(A.cc_d / A.Wmax);
     const T by = fma(dY, s, rel);
     T Jp[Tt];
 #pragma unroll
@@ -314,12 +323,11 @@ __global__ __launch_bounds__(256) void k_packet_diag(const BwdAngle* __restrict_
     for (int jj = jlo; jj <= jhi; ++jj) {
       const int j = jb + jj;
       const bool inb = active && j >= 0 && j < nb;
+      // a bin off the detector (or an idle lane) gets weight 0 through its intercept
+      const T Ce = inb ? Cn : T(-1e30);
       T w[Tt];
 #pragma unroll
-      for (int x = 0; x < Tt; ++x) {
-        const T dist = fabs(T(jj) - Jp[x]);
-        w[x] = inb ? clamp01<T>(fma(-dist, Bq, Cq), Wm) : T(0);
-      }
+      for (int x = 0; x < Tt; ++x) w[x] = unit_clamp(fma(-fabs(T(jj) - Jp[x]), Bn, Ce));
 #pragma unroll
       for (int b = 0; b < L; ++b) {   // along x, in registers
 #pragma unroll
@@ -335,7 +343,7 @@ __global__ __launch_bounds__(256) void k_packet_diag(const BwdAngle* __restrict_
 #pragma unroll
       for (int x = 0; x < Tt; ++x) part[x] = fma(w[x], w[x], part[x]);
     }
-    const double wk = (k == 0 || k == khalf) ? 0.5 : 1.0;   // exact scaling
+    const double wk = ((k == 0 || k == khalf) ? 0.5 : 1.0) * A.Wmax * A.Wmax;
 #pragma unroll
     for (int x = 0; x < Tt; ++x) acc[x] += wk * (double)part[x];
   }
