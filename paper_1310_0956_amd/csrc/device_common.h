@@ -16,9 +16,9 @@ __device__ __forceinline__ T clamp01(T v, T hi) {
 }
 
 // Value of lane (lane ^ MASK) for MASK < 16, with DPP lane moves inside a row
-// of 16 lanes: xor 1 and 2 by quad permutes, 8 by a row rotation by 8, 4 by a
-// half-row mirror (i -> i ^ 7) followed by the quad permute i -> i ^ 3.
-// Larger masks use a general lane permute.
+// of 16 lanes: xor 1 and 2 by quad permutes, 8 by a row rotation by 8, 7 by a
+// half-row mirror, 4 by the half-row mirror followed by the quad permute
+// i -> i ^ 3.  Larger masks use a general lane permute.
 template <int MASK>
 __device__ __forceinline__ int xor_lane_b32(int v) {
   if constexpr (MASK == 1) return __builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, true);
@@ -26,6 +26,7 @@ __device__ __forceinline__ int xor_lane_b32(int v) {
   else if constexpr (MASK == 4)
     return __builtin_amdgcn_mov_dpp(__builtin_amdgcn_mov_dpp(v, 0x141, 0xF, 0xF, true), 0x1B, 0xF,
                                     0xF, true);
+  else if constexpr (MASK == 7) return __builtin_amdgcn_mov_dpp(v, 0x141, 0xF, 0xF, true);
   else if constexpr (MASK == 8) return __builtin_amdgcn_mov_dpp(v, 0x128, 0xF, 0xF, true);
   else return __shfl_xor(v, MASK, 64);
 }

@@ -228,12 +228,30 @@ void wmg_launch(const Geometry& g, WmgMode mode, const WmgArgs& a, hipStream_t s
 __device__ __forceinline__ float unit_clamp(float v) { return __builtin_amdgcn_fmed3f(v, 0.0f, 1.0f); }
 __device__ __forceinline__ double unit_clamp(double v) { return fmin(fmax(v, 0.0), 1.0); }
 
-// y stages of the transform: stage b exchanges with lane y ^ 2^b
+// y stages of the transform.  Stage b exchanges with lane y ^ m_b, where the
+// masks m_b = 1, 2, 7, 8, 16 (a basis of the tile's lane indices) each take
+// one DPP move (2^2 = 4 would take two).  In the coordinates y' of y over
+// that basis (y'_0 = y_0 ^ y_2, y'_1 = y_1 ^ y_2, y'_b = y_b otherwise) the
+// stages are the butterflies of a Walsh-Hadamard transform along y'_b, the
+// lane with y'_b = 0 keeping u + v: afterwards lane y holds, up to sign, the
+// coefficient of y frequency ywalsh_row(y) (the squares are summed, so the
+// sign does not matter).
+template <int B>
+constexpr int kYMask = B == 2 ? 7 : 1 << B;
+__device__ __forceinline__ int ywalsh_role(int y, int b) {
+  return b < 2 ? ((y >> b) ^ (y >> 2)) & 1 : (y >> b) & 1;
+}
+template <int L>
+__device__ __forceinline__ int ywalsh_row(int y) {
+  if constexpr (L < 3) return y;
+  const int y0 = y & 1, y1 = (y >> 1) & 1, y2 = (y >> 2) & 1;
+  return (y & ~7) | (y0 ^ y2) | ((y1 ^ y2) << 1) | ((y0 ^ y1 ^ y2) << 2);
+}
 template <typename T, int L, int B = 0>
 __device__ __forceinline__ void y_stages(T (&w)[1 << L], const T (&sgn)[L > 0 ? L : 1]) {
   if constexpr (B < L) {
 #pragma unroll
-    for (int x = 0; x < (1 << L); ++x) w[x] = fma(sgn[B], w[x], xor_lane<(1 << B)>(w[x]));
+    for (int x = 0; x < (1 << L); ++x) w[x] = fma(sgn[B], w[x], xor_lane<kYMask<B>>(w[x]));
     y_stages<T, L, B + 1>(w, sgn);
   }
 }
@@ -246,9 +264,10 @@ __device__ __forceinline__ void y_stages(T (&w)[1 << L], const T (&sgn)[L > 0 ? 
 // the registers of a lane, y stages across the tile's lanes); the squares are
 // summed per angle in the tile's precision and added to float64 sums, in a
 // fixed order (deterministic, no atomics).
-// The butterflies keep the low element as u + v and the high one as u - v, so
-// the coefficients land in the in-place layout of the apply (x frequency u at
-// tile column u, y frequency v at tile row v).
+// The x butterflies keep the low element as u + v and the high one as u - v,
+// so x frequency u lands in register u; each lane stores its sums in the row
+// of the y frequency it holds (y_stages), so the sums take the in-place layout
+// of the apply (x frequency u at tile column u, y frequency v at tile row v).
 //
 // Symmetries of the geometry cut the work by about eight (N tiles per side;
 // tile (tx, ty); each map below changes only the signs of the Walsh
@@ -291,8 +310,9 @@ __global__ __launch_bounds__(256) void k_packet_diag(const BwdAngle* __restrict_
   const T dY = T(y - 0.5 * (Tt - 1));
   T sgn[L > 0 ? L : 1];   // y stage b: +1 keeps u + v (low lane), -1 gives u - v (high lane)
 #pragma unroll
-  for (int b = 0; b < L; ++b) sgn[b] = ((y >> b) & 1) ? T(-1) : T(1);
-  double* const mine = S + ((size_t)tile * Tt + y) * Tt;   // this lane's tile row
+  for (int b = 0; b < L; ++b) sgn[b] = ywalsh_role(y, b) ? T(-1) : T(1);
+  // this lane's row of the tile's sums: that of the y frequency it ends with
+  double* const mine = S + ((size_t)tile * Tt + ywalsh_row<L>(y)) * Tt;
   double acc[Tt];
 #pragma unroll
   for (int x = 0; x < Tt; ++x) acc[x] = (first || !active) ? 0.0 : mine[x];
