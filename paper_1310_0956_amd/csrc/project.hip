@@ -230,24 +230,32 @@ struct Window {
 // Row range and per-band column windows of every block, computed once per
 // geometry (they depend on the geometry only).  Block (g, bx) covers angles
 // groups[g][0..8) and bins [32 bx, 32 bx + 31] (clipped to nb).
-//  - rows: [lo, hi], the union over the block's rays of the rows where the
-//    ray is within 1.5 columns of the image;
+//  - rows: [lo, hi], covering the rows where any of the block's rays is
+//    within 1.5 columns of the image (block_rows);
 //  - band b (rows [lo + b*BAND, min(lo + (b+1)*BAND - 1, hi)]): columns
 //    [c0, c1], the floor(P) range over the block's corner rays (first and
 //    last bin of each angle at the band's first and last row), widened by one
 //    column on each side for rounding and clamped to [-2, n+1].
 // Positions are linear in bin and row for each angle, so the corner rays
-// bound every ray of the block, and the row range's extremes over the bins
-// are at the first and last bin.
-__device__ __forceinline__ void ray_rows(const FwdAngle& ang, int j, int n, int& lo, int& hi) {
-  const double P0 = fma((double)j, ang.inv, ang.A0);
+// bound every ray of the block.
+// Rows of bins [jf, jl] of one angle: the ray of bin j is within 1.5 columns
+// of the image between rows (-1.5 - P0(j)) / slope and (n + 0.5 - P0(j)) /
+// slope, bounds linear in j, so their extremes over the bins are those of the
+// first and last bin, and the rows are taken from them before clipping to the
+// image (a ray between two that miss the image on either side may cross it).
+// Axis-parallel rays (slope 0) meet every row or none: the block meets them
+// all when its positions P0 reach [-1.5, n + 0.5].  Empty: lo > hi.
+__device__ __forceinline__ void block_rows(const FwdAngle& ang, int jf, int jl, int n, int& lo,
+                                           int& hi) {
+  const double Pf = fma((double)jf, ang.inv, ang.A0), Pl = fma((double)jl, ang.inv, ang.A0);
   lo = n;
   hi = -1;
   if (ang.slope == 0.0) {
-    if (P0 >= -1.5 && P0 <= n + 0.5) { lo = 0; hi = n - 1; }
+    if (fmax(Pf, Pl) >= -1.5 && fmin(Pf, Pl) <= n + 0.5) { lo = 0; hi = n - 1; }
   } else {
-    const double t1 = (-1.5 - P0) / ang.slope, t2 = (n + 0.5 - P0) / ang.slope;
-    const double tl = fmin(t1, t2), th = fmax(t1, t2);
+    const double a1 = (-1.5 - Pf) / ang.slope, a2 = (n + 0.5 - Pf) / ang.slope;
+    const double b1 = (-1.5 - Pl) / ang.slope, b2 = (n + 0.5 - Pl) / ang.slope;
+    const double tl = fmin(fmin(a1, a2), fmin(b1, b2)), th = fmax(fmax(a1, a2), fmax(b1, b2));
     lo = (int)fmin(fmax(0.0, ceil(tl)), (double)n);
     hi = (int)fmax(fmin((double)(n - 1), floor(th)), -1.0);
   }
@@ -277,9 +285,7 @@ __global__ __launch_bounds__(256) void k_fwd_windows(const FwdAngle* __restrict_
     const int k = groups[g * kSlots + s];
     if (k < 0) continue;
     int l, h;
-    ray_rows(ang[k], jfirst, n, l, h);
-    if (h >= l) { lo = min(lo, l); hi = max(hi, h); }
-    ray_rows(ang[k], jlast, n, l, h);
+    block_rows(ang[k], jfirst, jlast, n, l, h);
     if (h >= l) { lo = min(lo, l); hi = max(hi, h); }
   }
   if (b < 0) {

@@ -22,10 +22,13 @@ reco = pytest.importorskip("paper_1310_0956_amd")
 pytestmark = pytest.mark.gpu
 
 # (n, m, nb, levels, lam): the paper's 40^2 / 100 x 40 problem (one level),
-# two and three levels, Tikhonov, and an axis-only geometry whose coarsest
-# blocks are singular (pivots dropped)
+# two and three levels, Tikhonov, and axis-only geometries whose coarsest
+# blocks are singular (pivots dropped).  The factorisation runs in panels of
+# 16 unknowns: blocks of 400, 64, 36 (a ragged last panel), 16 (one panel),
+# 9 (less than one panel) and 36 with dropped pivots in every panel.
 APPLY_CASES = [(40, 100, 40, 2, 0.0), (32, 24, 46, 3, 0.0), (32, 24, 46, 3, 0.2),
-               (48, 30, 70, 4, 0.05), (16, 2, 9, 3, 0.0)]
+               (48, 30, 70, 4, 0.05), (16, 2, 9, 3, 0.0), (12, 6, 17, 3, 0.1),
+               (24, 2, 35, 3, 0.0)]
 
 
 @pytest.mark.parametrize("n,m,nb,lv,lam", APPLY_CASES)

@@ -46,6 +46,13 @@ CASES = [
     (40, 21, 57, 4, False),
     (40, 21, 57, 4, True),
     (24, 12, 35, 4, True),
+    # small images whose 32-bin forward blocks span the whole shadow: the first
+    # and last ray of a block miss the image on either side while the rays
+    # between them cross it (axis-parallel and sloped angles)
+    (24, 2, 35, 3, True),
+    (16, 2, 23, 3, False),
+    (14, 6, 33, 2, False),
+    (14, 6, 33, 2, True),
 ]
 TOL = {False: 1e-5, True: 1e-12}
 

@@ -31,6 +31,7 @@ CASES = [
     (48, 2, 70, 2, False),
     (32, 4, 45, 4, True),
     (16, 1, 1, 2, True),
+    (14, 6, 33, 2, True),   # blocks whose first and last rays miss the image
     (128, 37, 182, 3, False),
     (64, 90, 91, 5, False),
     (128, 37, 182, 5, True),
