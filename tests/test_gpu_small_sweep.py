@@ -11,8 +11,9 @@ measured against |W| |x| (|W|^T |y|), the scale of a sum's rounding: with a
 few angles and one bin an output can be a near-cancelling sum of a handful of
 random-sign terms, whose relative error is not a property of the kernel.
 A block that loses its rays or rows gives an error of order one on this scale.
-The packet diagonal is compared elementwise (same tolerances) where one
-wavelet level fits and the detector has more than one bin: with a single bin
+The packet diagonal is compared elementwise, and the WMG apply in relative L2
+(same tolerances), where one wavelet level fits and the detector has more than
+one bin: with a single bin
 some coefficients are zero in exact arithmetic and come out as rounding noise
 (about 1e-32 of the largest in the float64 oracle, 1e-15 in float32), where
 neither side's value means anything.
@@ -21,6 +22,7 @@ import numpy as np
 import pytest
 
 from gpu_common import check_diag_elementwise, oracle_d, to_gpu, to_np
+from oracle import wmg
 from oracle.geometry import Geometry as OG
 from oracle.projector import system_matrix
 
@@ -64,6 +66,11 @@ def test_small_geometry_sweep(n):
                           f"backward {ebt:.3e}", flush=True)
                 assert eb <= TOL[f64] and ebt <= TOL[f64]
                 if lv == 2 and nb > 1:
-                    check_diag_elementwise(g.packet_diagonal(), oracle_d(n, m, nb, 1), TOL[f64])
+                    d_ref = oracle_d(n, m, nb, 1)
+                    check_diag_elementwise(g.packet_diagonal(), d_ref, TOL[f64])
+                    for lam in (0.0, 0.37):
+                        z = to_np(g.wmg_apply(xs, lam=lam)).ravel()
+                        z_ref = np.ravel(wmg.apply_additive_diag(x_dev, d_ref + lam, 1))
+                        assert np.linalg.norm(z - z_ref) <= TOL[f64] * np.linalg.norm(z_ref)
                 checked += 1
     print(f"n={n}: {checked} geometry/precision pairs", flush=True)
