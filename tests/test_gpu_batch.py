@@ -89,6 +89,30 @@ def test_batch_matches_solo_small_mix():
         assert torch.equal(xs2[i], xs[i])
 
 
+def test_batch_matches_solo_tiny_and_large():
+    """Small images whose forward blocks span the whole shadow (rays missing the
+    image on either side, axis-parallel-only angles, one WMG level) batched
+    with a 1024^2 problem whose grid takes one thread per ray where the small
+    ones take two: every result equals its solo solve bit for bit."""
+    specs = [(24, 2, 35, 3), (14, 6, 33, 2), (5, 3, 8, 1), (31, 9, 45, 1), (16, 4, 23, 3),
+             (1024, 720, 1449, 3)]
+    print_case("batch tiny and large", specs)
+    gs = _geoms(specs)
+    bs = [_data(g, 3 + i, 7200 + i) for i, g in enumerate(gs)]
+    fixed = [5, 6, 4, 7, 5, 0]
+    tol = [1e-3] * 5 + [1e-3]
+    pre = [reco.PRECOND_WMG if lv > 1 else reco.PRECOND_NONE for (_, _, _, lv) in specs]
+    xs = [g.new_image() for g in gs]
+    infos = reco.solve_batch(gs, bs, xs, tol=tol, precond=pre, fixed_iters=fixed)
+    torch.cuda.synchronize()
+    for i, g in enumerate(gs):
+        xr, ir = _solo(g, bs[i], tol=tol[i], precond=pre[i], fixed_iters=fixed[i])
+        xb = xs[i].cpu().numpy()
+        assert infos[i]["iters"] == ir["iters"] and infos[i]["status"] == ir["status"], (i, infos[i], ir)
+        assert np.array_equal(xb, xr), (i, float(np.abs(xb - xr).max()))
+        assert np.abs(xb).max() > 0.0
+
+
 def test_batch_check_every_and_max_iter():
     """Iterations per graph replay and the iteration cap do not change results."""
     print_case("batch tick sizes")
