@@ -253,19 +253,25 @@ __device__ __forceinline__ void stage_load(Stage<T, MODE>& sg, const StageSrc& s
 
 // Window values: the sinogram operand, in the CGLS modes the residual after
 // the current step, r - alpha q (the forward projector of the next iteration
-// stores the same value), times the row's plateau Wm (one rounding; a float
-// FMA with alpha rounded to float moved 5-iteration float32 iterates at 512^2
-// past 1e-5 of the float64 oracle).
+// stores the same value up to rounding), times the row's plateau Wm.  In
+// float, alpha is split into two floats ah + al (equal to alpha within
+// 2^-48 relative): the inner FMA forms r - ah q exactly before its one
+// rounding, so the difference, which cancels as the residual shrinks, takes
+// only roundings of its own size (alpha rounded to float instead moved
+// 5-iteration float32 iterates at 512^2 past 1e-5 of the float64 oracle).
 template <typename T, int MODE>
 __device__ __forceinline__ void stage_store(const Stage<T, MODE>& sg, T* __restrict__ w,
                                             double alpha, int t) {
   T* row = w + (t / kRowLanes) * kWin + (t % kRowLanes);
+  const float ah = (float)alpha, al = (float)(alpha - (double)ah);
 #pragma unroll
   for (int i = 0; i < kPerThread; ++i) {
     const int h = i / kPerRow, e = i % kPerRow;   // row (first or second), element
     const T wm = h ? sg.wb : sg.wa;
     T v;
-    if constexpr (kCglsMode(MODE))
+    if constexpr (kCglsMode(MODE) && sizeof(T) == 4)
+      v = fmaf(-al, sg.q[i], fmaf(-ah, sg.q[i], sg.r[i])) * wm;
+    else if constexpr (kCglsMode(MODE))
       v = (T)(((double)sg.r[i] - alpha * (double)sg.q[i]) * (double)wm);
     else
       v = sg.r[i] * wm;
