@@ -10,11 +10,6 @@
 
 namespace reco {
 
-template <typename T>
-__device__ __forceinline__ T clamp01(T v, T hi) {
-  return v < T(0) ? T(0) : (v > hi ? hi : v);
-}
-
 // Value of lane (lane ^ MASK) for MASK < 16, with DPP lane moves inside a row
 // of 16 lanes: xor 1 and 2 by quad permutes, 8 by a row rotation by 8, 7 by a
 // half-row mirror, 4 by the half-row mirror followed by the quad permute
@@ -66,16 +61,6 @@ __device__ __forceinline__ double wave_sum(double v) {
   v += xor_lane<4>(v);
   v += xor_lane<8>(v);
   return (read_lane(v, 0) + read_lane(v, 16)) + (read_lane(v, 32) + read_lane(v, 48));
-}
-__device__ __forceinline__ int wave_min(int v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, 64));
-  return v;
-}
-__device__ __forceinline__ int wave_max(int v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
-  return v;
 }
 
 // Sum W values over a block of NW waves in a fixed order.  Result valid in
