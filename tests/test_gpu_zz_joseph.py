@@ -32,6 +32,7 @@ CASES = [
     (32, 4, 45, 4, True),
     (16, 1, 1, 2, True),
     (14, 6, 33, 2, True),   # blocks whose first and last rays miss the image
+    (160, 5, 227, 2, False),   # band windows wider than the LDS window: read from memory
     (128, 37, 182, 3, False),
     (64, 90, 91, 5, False),
     (128, 37, 182, 5, True),
