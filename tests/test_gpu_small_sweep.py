@@ -5,8 +5,8 @@ Joseph's kernel).
 Small images stress the forward projector's per-block set-up: a block of 32
 bins can span the whole shadow of the image, rays can miss it on either side
 or run along its edges, and bands are cut short.  The sweep takes sides from
-2 to 37 (even and odd), 1 to 9 angles (axis-parallel only, 45 degrees, odd
-counts) and detectors from one bin to wider than the image's diagonal, in
+2 to 37 (even and odd), 1 to 90 angles (axis-parallel only, 45 degrees, odd
+counts, many full groups of 8) and detectors from one bin to wider than the image's diagonal, in
 float32 (1e-5) and float64 (1e-12).  The error of each operator output is
 measured against |W| |x| (|W|^T |y|), the scale of a sum's rounding: with a
 few angles and one bin an output can be a near-cancelling sum of a handful of
@@ -42,7 +42,7 @@ reco = pytest.importorskip("paper_1310_0956_amd")
 pytestmark = pytest.mark.gpu
 
 SIDES = (2, 3, 5, 8, 13, 14, 17, 24, 31, 37)
-ANGLES = (1, 2, 3, 4, 6, 9)
+ANGLES = (1, 2, 3, 4, 6, 9, 45, 90)
 TOL = {False: 1e-5, True: 1e-12}
 
 
